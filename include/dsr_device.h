@@ -1,0 +1,230 @@
+/*
+ * dsr_device.h -- device API of the data-sharing runtime (HIP, gfx950).
+ *
+ * The calls mirror the runtime entry points of the paper's generic-mode
+ * scheme (section 4, Figures 2 and 3; section 5.1):
+ *   team_init     ~ __kmpc_kernel_init: carve the team's LDS into a control
+ *                   block and a stack, bind the team's HBM slab slot.
+ *   push / pop    the master's frame allocation on the per-team stack
+ *                   (section 5.3.1's shared depot; overflow to the HBM slab
+ *                   as in section 5.2's global fallback and section 7's
+ *                   runtime-managed global stack).
+ *   publish       ~ __kmpc_kernel_prepare_parallel + the first barrier of
+ *                   Figure 2: hand a frame reference and a body to workers.
+ *   await         ~ the worker's barrier + __kmpc_kernel_parallel of
+ *                   Figure 3: false means terminate.
+ *   end_parallel  ~ __kmpc_kernel_end_parallel + the second barrier.
+ *
+ * Roles (a wave64 rendering of section 4's warp-based split): the team's
+ * last wave is the master wave and its lane 0 the OpenMP master; every
+ * lane of the master wave runs the sequential code in lock-step (so the
+ * other 63 lanes can assist bulk copies), the other waves are workers.
+ * Master-only calls (push, pop, publish) must be made by the whole master
+ * wave with uniform arguments; only lane 0 writes the shared state.
+ *
+ * A frame is a value {space, offset, size}, never a raw pointer: bodies
+ * turn it into an LDS or HBM address with frame_lds / frame_hbm.
+ *
+ * LDS layout of a team (dynamic shared memory):
+ *   [header 64 B][frame table 16 x 16 B][per-wave reduction slots nw x 32 B]
+ *   [per-wave sub-stacks nw x DSR_SUB_BYTES][stack: lds_cap bytes]
+ */
+#ifndef DSR_DEVICE_H
+#define DSR_DEVICE_H
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DSR_MAX_FRAMES 16
+#define DSR_MAX_WAVES 16
+#define DSR_SUB_BYTES 64u
+#define DSR_ALIGN 16u
+
+namespace dsr {
+
+enum : uint32_t { SPACE_LDS = 0, SPACE_HBM = 1, SPACE_NONE = 2 };
+
+struct frame_t {
+    uint32_t space;
+    uint32_t off;
+    uint32_t size;     /* rounded to DSR_ALIGN */
+};
+
+/* Control-block header (first 64 bytes of the team's LDS). */
+struct cb_header {
+    uint32_t body;     /* published body id; 0 = terminate        */
+    uint32_t space;    /* published frame                          */
+    uint32_t off;
+    uint32_t size;
+    uint32_t loop;     /* published loop descriptor index          */
+    uint32_t sp_lds;   /* LDS stack pointer (bytes in use)         */
+    uint32_t sp_hbm;   /* HBM stack pointer                        */
+    uint32_t nframes;  /* live frames                              */
+    int32_t error;     /* team error (DSR_E_* or 0)                */
+    uint32_t bad;      /* OR of the workers' range flags           */
+    uint32_t pad[6];
+};
+
+/* Bytes of control block for a team of nw waves. */
+__host__ __device__ constexpr uint32_t cb_bytes(uint32_t nw)
+{
+    return 64u + DSR_MAX_FRAMES * 16u + nw * 32u + nw * DSR_SUB_BYTES;
+}
+
+struct team_t {
+    uint8_t *lds;        /* team's dynamic LDS base (control block)        */
+    uint8_t *stack_lds;  /* LDS stack base                                 */
+    uint8_t *stack_hbm;  /* this team's HBM slab slot                      */
+    uint32_t lds_cap;
+    uint32_t threshold;  /* frames larger than this go to HBM              */
+    uint32_t hbm_cap;
+    uint32_t nw;         /* waves in the team                              */
+    uint32_t wave;       /* this wave (uniform)                            */
+    uint32_t lane;
+};
+
+__device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+/* Make lane 0's LDS writes visible to the rest of its wave. */
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline cb_header *header(const team_t &T) { return (cb_header *)T.lds; }
+__device__ inline uint32_t *frame_table(const team_t &T) { return (uint32_t *)(T.lds + 64); }
+__device__ inline uint64_t *red_slot(const team_t &T, uint32_t w)
+{
+    return (uint64_t *)(T.lds + 64 + DSR_MAX_FRAMES * 16 + w * 32);
+}
+__device__ inline uint8_t *sub_stack(const team_t &T, uint32_t w)
+{
+    return T.lds + 64 + DSR_MAX_FRAMES * 16 + T.nw * 32 + w * DSR_SUB_BYTES;
+}
+
+/* ~__kmpc_kernel_init.  Called by every thread of the team; the master
+ * lane resets the stack.  The first barrier of the team (publish/await)
+ * orders this before any worker reads the control block. */
+__device__ inline team_t team_init(uint8_t *lds, uint32_t nw, uint32_t lds_cap,
+                                   uint32_t threshold, uint8_t *hbm_slot, uint32_t hbm_cap)
+{
+    team_t T;
+    T.lds = lds;
+    T.nw = nw;
+    T.stack_lds = lds + cb_bytes(nw);
+    T.stack_hbm = hbm_slot;
+    T.lds_cap = lds_cap;
+    T.threshold = threshold;
+    T.hbm_cap = hbm_cap;
+    T.wave = uniform(threadIdx.x >> 6);
+    T.lane = threadIdx.x & 63u;
+    if (T.wave == nw - 1 && T.lane == 0) {
+        cb_header *h = header(T);
+        h->body = 0;
+        h->sp_lds = 0;
+        h->sp_hbm = 0;
+        h->nframes = 0;
+        h->error = 0;
+        h->bad = 0;
+    }
+    return T;
+}
+
+/* Master wave: place a frame of nbytes (rounded up to 16).  LDS when it
+ * fits and is not above the overflow threshold, else the HBM slot, else
+ * SPACE_NONE (out of memory; nothing is allocated). */
+__device__ inline frame_t push(team_t &T, uint32_t nbytes)
+{
+    cb_header *h = header(T);
+    const uint32_t size = (nbytes + DSR_ALIGN - 1) & ~(DSR_ALIGN - 1);
+    uint32_t spl = uniform(h->sp_lds), sph = uniform(h->sp_hbm), nf = uniform(h->nframes);
+    frame_t f;
+    f.size = size;
+    if (size <= T.threshold && size <= T.lds_cap - spl) {
+        f.space = SPACE_LDS; f.off = spl; spl += size;
+    } else if (size <= T.hbm_cap - sph) {
+        f.space = SPACE_HBM; f.off = sph; sph += size;
+    } else {
+        f.space = SPACE_NONE; f.off = 0;
+        return f;
+    }
+    wave_sync();
+    if (T.lane == 0) {
+        h->sp_lds = spl;
+        h->sp_hbm = sph;
+        uint32_t *ft = frame_table(T) + 4 * nf;
+        ft[0] = f.space; ft[1] = f.off; ft[2] = f.size; ft[3] = 0;
+        h->nframes = nf + 1;
+    }
+    wave_sync();
+    return f;
+}
+
+/* Master wave: pop the top frame.  Returns false if f is not the top
+ * (the host rejects such programs before launch; this is a guard). */
+__device__ inline bool pop(team_t &T, frame_t f)
+{
+    cb_header *h = header(T);
+    uint32_t nf = uniform(h->nframes);
+    if (nf == 0) return false;
+    const uint32_t *ft = frame_table(T) + 4 * (nf - 1);
+    if (uniform(ft[0]) != f.space || uniform(ft[1]) != f.off) return false;
+    uint32_t spl = uniform(h->sp_lds), sph = uniform(h->sp_hbm);
+    wave_sync();
+    if (T.lane == 0) {
+        if (f.space == SPACE_LDS) h->sp_lds = spl - f.size; else h->sp_hbm = sph - f.size;
+        h->nframes = nf - 1;
+    }
+    wave_sync();
+    return true;
+}
+
+/* Master wave: hand frame f and body to the workers (barrier 1). */
+__device__ inline void publish(team_t &T, frame_t f, uint32_t body, uint32_t loop)
+{
+    cb_header *h = header(T);
+    if (T.lane == 0) {
+        h->body = body;
+        h->space = f.space;
+        h->off = f.off;
+        h->size = f.size;
+        h->loop = loop;
+    }
+    __syncthreads();
+}
+
+/* Worker waves: wait for work (barrier 1).  Returns false on terminate. */
+__device__ inline bool await(team_t &T, uint32_t *body, frame_t *f, uint32_t *loop)
+{
+    __syncthreads();
+    cb_header *h = header(T);
+    *body = uniform(h->body);
+    f->space = uniform(h->space);
+    f->off = uniform(h->off);
+    f->size = uniform(h->size);
+    *loop = uniform(h->loop);
+    return *body != 0;
+}
+
+/* Every participating wave: deposit its reduction partial (a 192-bit
+ * integer, three 64-bit words, low first) and its range flag, then join
+ * (barrier 2).  Waves that did not run the body pass zeros. */
+__device__ inline void end_parallel(team_t &T, uint64_t w0, uint64_t w1, uint64_t w2, uint32_t bad)
+{
+    if (T.lane == 0) {
+        uint64_t *r = red_slot(T, T.wave);
+        r[0] = w0; r[1] = w1; r[2] = w2;
+        if (bad) atomicOr(&header(T)->bad, 1u);
+    }
+    __syncthreads();
+}
+
+/* Frame address in LDS or in the team's HBM slot. */
+__device__ inline uint8_t *frame_lds(const team_t &T, frame_t f) { return T.stack_lds + f.off; }
+__device__ inline uint8_t *frame_hbm(const team_t &T, frame_t f) { return T.stack_hbm + f.off; }
+
+} // namespace dsr
+
+#endif /* DSR_DEVICE_H */

@@ -445,6 +445,8 @@ def run_team(team, program, interleaving=None):
                 if len(init) < op.nbytes:
                     team.write(f, len(init), bytes(op.nbytes - len(init)), "master")
             elif isinstance(op, Pop):
+                if not team.frames:
+                    raise SimError("UNDERFLOW", "pop on an empty stack")
                 if op.frame >= len(pushed):
                     raise SimError("STATE", "pop of a frame never pushed")
                 team.pop(op.frame)

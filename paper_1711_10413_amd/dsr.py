@@ -1,0 +1,230 @@
+"""ctypes binding of libdsr.so: the C ABI of include/dsr.h, same names.
+
+Argument marshalling only -- every step of a region runs in the HIP
+kernels.  Device buffers are passed as integer addresses (for instance a
+PyTorch tensor's ``data_ptr()``) and streams as integer handles
+(``torch.cuda.current_stream().cuda_stream``).  Importing this module
+fails loudly if the library has not been built.
+"""
+import ctypes as C
+import os
+import struct
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdsr.so")
+
+DSR_OK = 0
+DSR_E_INVAL = -1
+DSR_E_NOMEM = -2
+DSR_E_LDS = -3
+DSR_E_UNDERFLOW = -4
+DSR_E_ORDER = -5
+DSR_E_LIVE = -6
+DSR_E_STATE = -7
+DSR_E_BUSY = -8
+DSR_E_HIP = -9
+DSR_E_RANGE = -10
+ERROR_NAMES = {DSR_E_INVAL: "INVAL", DSR_E_NOMEM: "NOMEM", DSR_E_LDS: "LDS",
+               DSR_E_UNDERFLOW: "UNDERFLOW", DSR_E_ORDER: "ORDER", DSR_E_LIVE: "LIVE",
+               DSR_E_STATE: "STATE", DSR_E_BUSY: "BUSY", DSR_E_HIP: "HIP",
+               DSR_E_RANGE: "RANGE"}
+
+DSR_BODY_TERMINATE = 0
+DSR_BODY_AFFINE_XOR = 1
+DSR_BODY_FMA_CHAIN = 2
+DSR_BODY_GATHER = 3
+DSR_BODY_GATHER_NESTED = 4
+
+DSR_F_TRACE = 1
+DSR_TRACE_WORDS = 96
+
+# the exported C entry points (include/dsr.h)
+EXPORTS = ("dsr_init", "dsr_destroy", "dsr_region_begin", "dsr_push", "dsr_publish",
+           "dsr_pop", "dsr_launch", "dsr_region_sync", "dsr_region_reduction",
+           "dsr_region_trace", "dsr_region_elapsed", "dsr_region_free", "dsr_strerror")
+
+
+class dsr_config(C.Structure):
+    _fields_ = [("wg_size", C.c_uint32), ("lds_slab_bytes", C.c_uint32),
+                ("overflow_threshold", C.c_uint32), ("master_joins", C.c_uint32),
+                ("hbm_slab_bytes", C.c_uint64), ("max_teams", C.c_uint32),
+                ("flags", C.c_uint32)]
+
+
+class dsr_loop(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("chunk", C.c_uint64), ("in_", C.c_void_p),
+                ("out", C.c_void_p), ("ni", C.c_uint32), ("nf", C.c_uint32),
+                ("alen", C.c_uint32), ("arrays", C.c_uint32), ("len", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class DsrError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = code
+        self.name = ERROR_NAMES.get(code, str(code))
+        super().__init__("%s: %s (%s)" % (where, strerror(code), self.name))
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if libdsr.so is missing)."""
+    global _lib
+    if _lib is None:
+        # PyTorch ships its own copy of the HIP runtime under the same soname
+        # as ROCm's; load it first so that one runtime serves the process and
+        # device pointers and streams from torch are valid here.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libdsr.so is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P, u32, i32 = C.c_void_p, C.c_uint32, C.c_int32
+        sig = {
+            "dsr_init": [C.POINTER(P), C.POINTER(dsr_config), C.c_int],
+            "dsr_destroy": [P],
+            "dsr_region_begin": [P, i32, C.POINTER(P)],
+            "dsr_push": [P, u32, P, u32, u32, C.POINTER(i32)],
+            "dsr_publish": [P, i32, i32, C.POINTER(dsr_loop)],
+            "dsr_pop": [P, i32],
+            "dsr_launch": [P, P],
+            "dsr_region_sync": [P],
+            "dsr_region_reduction": [P, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_uint64)],
+            "dsr_region_trace": [P, i32, C.POINTER(u32), u32],
+            "dsr_region_elapsed": [P, C.POINTER(C.c_float)],
+            "dsr_region_free": [P],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.dsr_strerror.argtypes = [C.c_int]
+        L.dsr_strerror.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(code):
+    return lib().dsr_strerror(code).decode()
+
+
+def _check(rc, where):
+    if rc != DSR_OK:
+        raise DsrError(rc, where)
+    return rc
+
+
+# ---- thin wrappers with the C names ---------------------------------------
+def dsr_init(wg_size=256, lds_slab_bytes=65536, overflow_threshold=0, master_joins=0,
+             hbm_slab_bytes=1 << 20, max_teams=4096, flags=0, device=0):
+    cfg = dsr_config(wg_size, lds_slab_bytes, overflow_threshold, master_joins,
+                     hbm_slab_bytes, max_teams, flags)
+    ctx = C.c_void_p()
+    _check(lib().dsr_init(C.byref(ctx), C.byref(cfg), device), "dsr_init")
+    return ctx
+
+
+def dsr_destroy(ctx):
+    return _check(lib().dsr_destroy(ctx), "dsr_destroy")
+
+
+def dsr_region_begin(ctx, teams):
+    r = C.c_void_p()
+    _check(lib().dsr_region_begin(ctx, teams, C.byref(r)), "dsr_region_begin")
+    return r
+
+
+def dsr_push(region, nbytes, init=b"", init_stride=0, init_bytes=None):
+    """Push a frame of ``nbytes``.  Without ``init_stride`` the frame's first
+    len(init) bytes come from ``init``; with it, ``init`` holds one image per
+    team, ``init_stride`` bytes apart, of which ``init_bytes`` are copied."""
+    init = bytes(init)
+    buf = C.create_string_buffer(init, len(init)) if init else None
+    if init_bytes is None:
+        init_bytes = min(init_stride, nbytes) if init_stride else len(init)
+    h = C.c_int32()
+    _check(lib().dsr_push(region, nbytes, buf, init_bytes, init_stride, C.byref(h)), "dsr_push")
+    return h.value
+
+
+def dsr_publish(region, frame, body, n, inp=0, out=0, chunk=0, ni=0, nf=0, alen=0, arrays=0,
+                length=0):
+    L = dsr_loop(n, chunk, inp or None, out or None, ni, nf, alen, arrays, length, 0)
+    return _check(lib().dsr_publish(region, frame, body, C.byref(L)), "dsr_publish")
+
+
+def dsr_pop(region, frame):
+    return _check(lib().dsr_pop(region, frame), "dsr_pop")
+
+
+def dsr_launch(region, stream=0):
+    return _check(lib().dsr_launch(region, stream or None), "dsr_launch")
+
+
+def dsr_region_sync(region):
+    """Device status of the last launch (0 or a negative DSR_E_* code)."""
+    rc = lib().dsr_region_sync(region)
+    if rc in (DSR_E_INVAL, DSR_E_STATE, DSR_E_HIP):
+        raise DsrError(rc, "dsr_region_sync")
+    return rc
+
+
+def dsr_region_reduction(region, index):
+    """(int64 sum, float sum, exact total as a Python int in 2**-75 units)."""
+    i = C.c_int64()
+    f = C.c_double()
+    w = (C.c_uint64 * 3)()
+    _check(lib().dsr_region_reduction(region, index, C.byref(i), C.byref(f), w),
+           "dsr_region_reduction")
+    v = w[0] | (w[1] << 64) | (w[2] << 128)
+    if v >> 191:
+        v -= 1 << 192
+    return i.value, f.value, v
+
+
+def dsr_region_trace(region, team):
+    buf = (C.c_uint32 * DSR_TRACE_WORDS)()
+    _check(lib().dsr_region_trace(region, team, buf, DSR_TRACE_WORDS), "dsr_region_trace")
+    t = list(buf)
+    k = t[0]
+    return {"placements": [(("lds", "hbm")[t[1 + 3 * p]], t[2 + 3 * p], t[3 + 3 * p])
+                           for p in range(min(k, 16))],
+            "barriers": t[49:65], "inner_pushes": t[65:81],
+            "error": C.c_int32(t[81]).value}
+
+
+def dsr_region_elapsed(region):
+    ms = C.c_float()
+    _check(lib().dsr_region_elapsed(region, C.byref(ms)), "dsr_region_elapsed")
+    return ms.value
+
+
+def dsr_region_free(region):
+    return _check(lib().dsr_region_free(region), "dsr_region_free")
+
+
+# ---- frame images for the bodies' layouts (include/dsr.h) -----------------
+def affine_xor_frame(a, b, c, d):
+    """[0,8) int64 sum = 0; int32 a, b, c, d."""
+    return struct.pack("<qiiii", 0, a, b, c, d)
+
+
+def fma_chain_frame(s_i32, s_f64, arr=None):
+    """[0,24) exact sum = 0; fp64 scalars; int32 scalars; array at the next
+    16-byte boundary.  Returns (bytes, declared size)."""
+    s_i32 = np.asarray(s_i32, np.int32)
+    s_f64 = np.asarray(s_f64, np.float64)
+    head = bytes(24) + s_f64.tobytes() + s_i32.tobytes()
+    if arr is not None and len(arr):
+        pad = (-len(head)) % 16
+        head = head + bytes(pad) + np.asarray(arr, np.int32).tobytes()
+    return head, len(head)
+
+
+def gather_frame(arrays):
+    return b"".join(np.asarray(a, np.int32).tobytes() for a in arrays)

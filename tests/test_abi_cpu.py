@@ -1,0 +1,131 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every
+entry point its header declares, and rejects bad programs on the host with
+the same error the contention-group simulator gives."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1711_10413_amd import dsr as D
+from oracle import sim as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if not h.endswith(".h") or h == "dsr_device.h":
+            continue
+        text = open(os.path.join(ROOT, "include", h)).read()
+        names |= set(re.findall(r"^\s*(?:int|const char \*)\s*(dsr_\w+)\s*\(", text, re.M))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert names >= set(D.EXPORTS)
+    lib = D.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def host_ctx(**kw):
+    return D.dsr_init(device=-1, **kw)
+
+
+def test_bad_configs():
+    for kw, code in [({"wg_size": 100}, D.DSR_E_INVAL), ({"wg_size": 2048}, D.DSR_E_INVAL),
+                     ({"max_teams": 0}, D.DSR_E_INVAL), ({"lds_slab_bytes": 20}, D.DSR_E_INVAL),
+                     ({"lds_slab_bytes": 160 * 1024}, D.DSR_E_LDS),
+                     ({"hbm_slab_bytes": 17}, D.DSR_E_INVAL), ({"flags": 8}, D.DSR_E_INVAL)]:
+        with pytest.raises(D.DsrError) as e:
+            host_ctx(**kw)
+        assert e.value.code == code, kw
+    ctx = host_ctx(lds_slab_bytes=160 * 1024 - 1024)     # fits with a 4-wave control block
+    D.dsr_destroy(ctx)
+
+
+def run_host(prog_ops, teams=2):
+    """Apply a list of ('push', n) / ('pop', h) / ('publish', h) to a region
+    of a host-only context; returns the first error name or None, and then
+    tries to launch (LIVE if a frame remains)."""
+    ctx = host_ctx(lds_slab_bytes=64, hbm_slab_bytes=1024)
+    r = D.dsr_region_begin(ctx, teams)
+    try:
+        for op, arg in prog_ops:
+            if op == "push":
+                D.dsr_push(r, arg)
+            elif op == "pop":
+                D.dsr_pop(r, arg)
+            else:
+                D.dsr_publish(r, arg, D.DSR_BODY_AFFINE_XOR, 8, out=0x1000)
+        D.dsr_launch(r)
+    except D.DsrError as e:
+        return e.name
+    finally:
+        D.dsr_region_free(r)
+        D.dsr_destroy(ctx)
+    return None
+
+
+def test_host_errors_match_simulator():
+    out = np.zeros(8, np.int64)
+    cases = [
+        ([("push", 24), ("publish", 0)], [S.Push(24), S.Publish(0, "affine_xor", {"n": 8, "out": out})]),
+        ([("push", 24), ("push", 8), ("pop", 0)], [S.Push(24), S.Push(8), S.Pop(0)]),
+        ([("pop", 0)], [S.Pop(0)]),
+        ([("push", 24), ("pop", 0), ("pop", 0)], [S.Push(24), S.Pop(0), S.Pop(0)]),
+        ([("push", 24), ("pop", 0), ("publish", 0)],
+         [S.Push(24), S.Pop(0), S.Publish(0, "affine_xor", {"n": 8, "out": out})]),
+    ]
+    for host_prog, sim_prog in cases:
+        got = run_host(host_prog)
+        tr, _ = S.run_region(sim_prog, 2, S.Config(lds_bytes=64, hbm_bytes=1024))
+        want = tr[0].error
+        # a pop of a never-pushed / dead handle is a state error on both sides
+        assert got == want, (host_prog, got, want)
+    # a host-only context validates but cannot launch
+    assert run_host([("push", 24), ("pop", 0)]) == "STATE"
+
+
+def test_publish_validation():
+    ctx = host_ctx()
+    r = D.dsr_region_begin(ctx, 4)
+    f = D.dsr_push(r, 16)
+    bad = [
+        dict(body=D.DSR_BODY_AFFINE_XOR, n=8, out=0x1000),                  # frame < 24 B
+        dict(body=D.DSR_BODY_FMA_CHAIN, n=8, inp=0x1000, out=0x2000, ni=1),  # frame < 28 B
+        dict(body=D.DSR_BODY_GATHER, n=8, out=0x1000, arrays=1, length=8),   # frame < 32 B
+        dict(body=D.DSR_BODY_GATHER, n=8, out=0x1000, arrays=0, length=4),
+        dict(body=99, n=8, out=0x1000),
+        dict(body=D.DSR_BODY_GATHER, n=64, out=0x1000, arrays=1, length=4, chunk=8),  # uncovered
+        dict(body=D.DSR_BODY_GATHER, n=8, out=0, arrays=1, length=4),
+    ]
+    for kw in bad:
+        body = kw.pop("body")
+        with pytest.raises(D.DsrError) as e:
+            D.dsr_publish(r, f, body, **kw)
+        assert e.value.code == D.DSR_E_INVAL, kw
+    D.dsr_publish(r, f, D.DSR_BODY_GATHER, 8, out=0x1000, arrays=1, length=4)
+    D.dsr_pop(r, f)
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+
+
+def test_region_limits():
+    ctx = host_ctx(max_teams=8)
+    with pytest.raises(D.DsrError):
+        D.dsr_region_begin(ctx, 9)
+    r = D.dsr_region_begin(ctx, 8)
+    hs = [D.dsr_push(r, 16) for _ in range(16)]
+    with pytest.raises(D.DsrError):
+        D.dsr_push(r, 16)                       # deeper than 16 live frames
+    for h in reversed(hs):
+        D.dsr_pop(r, h)
+    with pytest.raises(D.DsrError) as e:
+        D.dsr_pop(r, 0)
+    assert e.value.code == D.DSR_E_UNDERFLOW
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)

@@ -254,7 +254,7 @@ def test_sim_runtime_errors():
     cases = [
         ([S.Push(24, init), pub], "LIVE"),
         ([S.Push(24, init), S.Push(8), S.Pop(0), S.Pop(1)], "ORDER"),
-        ([S.Pop(0)], "STATE"),
+        ([S.Pop(0)], "UNDERFLOW"),
         ([S.Push(24, init), S.Pop(0), S.Pop(0)], "UNDERFLOW"),
         ([S.Push(24, init), S.Pop(0), pub], "STATE"),
         ([S.Push(4096)], "NOMEM"),
