@@ -98,6 +98,7 @@ extern "C" {
 
 /* ---- configuration -------------------------------------------------------- */
 #define DSR_F_TRACE        1u  /* record frame placements and barrier counts   */
+#define DSR_F_TIMING       2u  /* record HIP events around every launch        */
 
 typedef struct dsr_config {
     uint32_t wg_size;            /* threads per team: multiple of 64 in [64, 1024] */
@@ -123,8 +124,25 @@ typedef struct dsr_loop {
     uint32_t alen;     /* FMA_CHAIN: array length (0 = none)                    */
     uint32_t arrays;   /* GATHER: number of arrays A (1..16)                     */
     uint32_t len;      /* GATHER: elements per array                            */
-    uint32_t reserved;
+    uint32_t schedule; /* DSR_SCHED_STATIC or DSR_SCHED_DYNAMIC_TAIL            */
+    uint32_t tail_pct; /* DYNAMIC_TAIL: percent of iterations claimed dynamically
+                          (1..99; 0 = 25)                                        */
+    uint32_t block;    /* DYNAMIC_TAIL: iterations per claim (multiple of 128,
+                          at most 65536; 0 = 1024)                               */
 } dsr_loop;
+
+/* Loop schedules.
+ * STATIC: team t runs [t*chunk, min(n, (t+1)*chunk)); its worker lanes take
+ *   the iterations cyclically.
+ * DYNAMIC_TAIL: the first (100 - tail_pct)% of the iterations are split
+ *   statically as above (chunk is computed by the runtime and must be 0 on
+ *   input); the rest is cut into blocks of `block` iterations that worker
+ *   waves of any team claim one at a time from a device counter, so teams
+ *   that run faster take more of the tail.  Allowed only when every team's
+ *   copy of the published frame is initialised identically (no init_stride),
+ *   since a block may run on any team.  Results are the same as STATIC's. */
+#define DSR_SCHED_STATIC        0
+#define DSR_SCHED_DYNAMIC_TAIL  1
 
 typedef struct dsr_ctx dsr_ctx;
 typedef struct dsr_region dsr_region;
@@ -186,12 +204,19 @@ int dsr_region_reduction(dsr_region *r, int32_t index, int64_t *i64, double *f64
  *   [1 + 3p .. 3 + 3p]    push p: space (0 LDS, 1 HBM), offset, rounded size
  *   [49 .. 64]            barriers passed by wave 0 .. 15
  *   [65 .. 80]            inner frames pushed by wave 0 .. 15 (nested body)
- *   [81]                  team error code                                   */
-#define DSR_TRACE_WORDS 96
+ *   [81]                  team error code
+ *   [82 .. 83]            wall clock (100 MHz, low word first) when the
+ *                         workers were released for the first publish
+ *   [84 .. 85]            wall clock when the last publish joined
+ *   [86]                  low word of the wall clock at team start
+ *   [96 + 2w, 97 + 2w]    low words of the wall clock when wave w started
+ *                         and finished its share of the last body it ran   */
+#define DSR_TRACE_WORDS 128
 int dsr_region_trace(dsr_region *r, int32_t team, uint32_t *buf, uint32_t n);
 
 /* Duration of the last launch's kernel in milliseconds, from HIP events
- * recorded around it on its stream (after dsr_region_sync). */
+ * recorded around it on its stream (needs DSR_F_TIMING; DSR_E_STATE
+ * otherwise). */
 int dsr_region_elapsed(dsr_region *r, float *ms);
 
 /* Release a region's host and device memory (syncs its last launch). */

@@ -56,6 +56,7 @@ struct dsr_region {
     dsr_dresult *d_result;
     uint32_t *d_trace;
     hipEvent_t ev0, ev1;
+    bool timed;                         /* ev0 was recorded by the last launch */
     bool launched;
     dsr_dresult h_result;
     bool have_result;
@@ -88,7 +89,7 @@ extern "C" int dsr_init(dsr_ctx **out, const dsr_config *cfg, int device)
     if (c.max_teams == 0) return DSR_E_INVAL;
     if (c.hbm_slab_bytes > 0xFFFFFFF0ull || (c.hbm_slab_bytes & 15u)) return DSR_E_INVAL;
     if (c.lds_slab_bytes & 15u) return DSR_E_INVAL;
-    if (c.flags & ~DSR_F_TRACE) return DSR_E_INVAL;
+    if (c.flags & ~(DSR_F_TRACE | DSR_F_TIMING)) return DSR_E_INVAL;
     const uint32_t nw = c.wg_size / 64;
     const uint64_t lds = (uint64_t)dsr::cb_bytes(nw) + c.lds_slab_bytes;
     uint32_t lds_max = kDefaultLdsPerWg;
@@ -152,6 +153,7 @@ extern "C" int dsr_region_begin(dsr_ctx *ctx, int32_t teams, dsr_region **out)
     r->d_result = nullptr;
     r->d_trace = nullptr;
     r->ev0 = r->ev1 = nullptr;
+    r->timed = false;
     r->launched = false;
     r->have_result = false;
     *out = r;
@@ -209,12 +211,30 @@ extern "C" int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr
     const uint32_t nb = r->nbytes[frame];
     if (L.n > 0x7FFFFFFFull) return DSR_E_INVAL;
     uint64_t chunk = L.chunk;
-    if (chunk == 0) {
-        chunk = (L.n + r->teams - 1) / r->teams;
-        chunk = (chunk + 63) & ~63ull;
-        if (chunk == 0) chunk = 64;
+    uint64_t dyn_start = L.n;
+    uint32_t block = 0;
+    if (L.schedule == DSR_SCHED_STATIC) {
+        if (chunk == 0) {
+            chunk = (L.n + r->teams - 1) / r->teams;
+            chunk = (chunk + 63) & ~63ull;
+            if (chunk == 0) chunk = 64;
+        }
+        if (chunk * (uint64_t)r->teams < L.n) return DSR_E_INVAL;
+    } else if (L.schedule == DSR_SCHED_DYNAMIC_TAIL) {
+        if (chunk != 0) return DSR_E_INVAL;
+        const uint32_t pct = L.tail_pct ? L.tail_pct : 25;
+        block = L.block ? L.block : 1024;
+        if (pct > 99 || (block & 127u) || block > 65536) return DSR_E_INVAL;
+        /* a block can run on any team: every team's frame must be the same */
+        for (const dsr_op &o : r->ops)
+            if (o.kind == DSR_OP_PUSH && o.frame == (uint32_t)frame && o.init_stride) return DSR_E_INVAL;
+        chunk = (L.n * (100 - pct) / 100) / r->teams;
+        chunk &= ~63ull;
+        dyn_start = chunk * (uint64_t)r->teams;
+        if (chunk == 0) chunk = 64;   /* all of the loop is the dynamic tail */
+    } else {
+        return DSR_E_INVAL;
     }
-    if (chunk * (uint64_t)r->teams < L.n) return DSR_E_INVAL;
     if (L.n && !L.out) return DSR_E_INVAL;
     bool reduces = false;
     switch (body) {
@@ -228,8 +248,12 @@ extern "C" int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr
         uint64_t need = 24 + 8ull * L.nf + 4ull * L.ni;
         if (L.alen) need = ((need + 15) & ~15ull) + 4ull * L.alen;
         if (nb < need) return DSR_E_INVAL;
-        /* per-lane 128-bit sums stay exact for up to 2^20 values per lane */
-        if (chunk > (1ull << 26)) return DSR_E_INVAL;
+        /* a lane's fp64 bins stay exact for up to 2^16 values; the static
+         * share is bounded here, dynamic blocks flush the bins as they go */
+        {
+            const uint64_t lanes = 64ull * (r->ctx->cfg.master_joins ? r->ctx->nw : r->ctx->nw - 1);
+            if ((chunk + lanes - 1) / lanes > (1ull << 15)) return DSR_E_INVAL;
+        }
         if (L.alen == 0 && L.ni == 16 && L.nf == 16 && r->variant < 1) r->variant = 1;
         if (L.alen == 0 && L.ni == 32 && L.nf == 32) r->variant = 2;
         reduces = true;
@@ -237,6 +261,7 @@ extern "C" int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr
     }
     case DSR_BODY_GATHER:
     case DSR_BODY_GATHER_NESTED:
+        if (body == DSR_BODY_GATHER_NESTED && L.schedule != DSR_SCHED_STATIC) return DSR_E_INVAL;
         if (L.arrays < 1 || L.arrays > 16 || L.len < 1) return DSR_E_INVAL;
         if ((uint64_t)nb < 4ull * L.arrays * L.len) return DSR_E_INVAL;
         break;
@@ -254,6 +279,9 @@ extern "C" int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr
     dl.alen = L.alen;
     dl.arrays = L.arrays;
     dl.len = L.len;
+    dl.schedule = L.schedule;
+    dl.block = block;
+    dl.dyn_start = dyn_start;
     dsr_op op{};
     op.kind = DSR_OP_PUBLISH;
     op.frame = (uint32_t)depth;
@@ -361,9 +389,12 @@ extern "C" int dsr_launch(dsr_region *r, void *stream)
     C.threshold = c->threshold;
     C.master_joins = c->cfg.master_joins ? 1u : 0u;
     C.trace = (c->cfg.flags & DSR_F_TRACE) ? 1u : 0u;
-    if (hipEventRecord(r->ev0, s) != hipSuccess) return DSR_E_HIP;
-    if (dsr_launch_region_kernel(&R, &C, c->cfg.wg_size, c->lds_bytes, r->variant, stream) != 0) return DSR_E_HIP;
+    const bool timing = (c->cfg.flags & DSR_F_TIMING) != 0;
+    if (timing && hipEventRecord(r->ev0, s) != hipSuccess) return DSR_E_HIP;
+    if (dsr_launch_region_kernel(&R, &C, c->cfg.wg_size, c->lds_bytes, r->variant, stream) != 0)
+        return DSR_E_HIP;
     if (hipEventRecord(r->ev1, s) != hipSuccess) return DSR_E_HIP;
+    r->timed = timing;
     r->launched = true;
     r->have_result = false;
     return DSR_OK;
@@ -408,7 +439,7 @@ extern "C" int dsr_region_trace(dsr_region *r, int32_t team, uint32_t *buf, uint
 extern "C" int dsr_region_elapsed(dsr_region *r, float *ms)
 {
     if (!r || !ms) return DSR_E_INVAL;
-    if (!r->launched) return DSR_E_STATE;
+    if (!r->launched || !r->timed) return DSR_E_STATE;
     if (hipEventSynchronize(r->ev1) != hipSuccess) return DSR_E_HIP;
     return hipEventElapsedTime(ms, r->ev0, r->ev1) == hipSuccess ? DSR_OK : DSR_E_HIP;
 }

@@ -29,11 +29,12 @@ struct dsr_op {
 
 struct dsr_dloop {
     uint64_t n;
-    uint64_t chunk;
+    uint64_t chunk;        /* static iterations per team                    */
     const void *in;
     void *out;
     uint32_t ni, nf, alen, arrays;
-    uint32_t len, pad0, pad1, pad2;
+    uint32_t len, schedule, block, pad;
+    uint64_t dyn_start;    /* first iteration of the dynamic tail (= n if none) */
 };
 
 /* Per-launch result block (device memory, written by the last team). */
@@ -42,6 +43,7 @@ struct dsr_dresult {
     uint32_t arrived;      /* teams that finished; reset by the last team   */
     int32_t final_error;   /* the launch's error, written by the last team  */
     uint32_t done;         /* launch counter, bumped by the last team       */
+    uint32_t claim[DSR_MAX_LOOPS]; /* dynamic-tail block counters; reset by the last team */
     uint64_t fixed[DSR_MAX_RED][3];
     double f64[DSR_MAX_RED];
     int64_t i64[DSR_MAX_RED];

@@ -11,11 +11,16 @@
  * variable and join.  After its program the master publishes TERMINATE;
  * the last team to finish combines the teams' partial reductions.
  *
- * Exact fp64 reduction: every loop value y is converted exactly to a signed
- * integer number of 2^-75 units (it must lie on that grid with |y| < 2^32)
- * and summed in 128-bit (lane) and 192-bit (wave, team, region) integer
- * arithmetic; the region total is rounded to double once, so the result is
- * the correctly rounded sum whatever the team, wave or launch layout.
+ * Exact fp64 reduction: every loop value y must be a multiple of 2^-75 with
+ * |y| < 2^32.  Each lane splits y exactly into three parts on the grids
+ * 2^-5, 2^-40 and 2^-75 (y + C - C rounding with a constant C whose last
+ * bit has the grid's weight) and adds each part into its own fp64 bin.  A
+ * bin's values have at most 37 significant bits above its grid, so up to
+ * 2^16 of them sum exactly in fp64.  At the end of the loop each lane turns
+ * its bins into one signed 192-bit integer of 2^-75 units; waves, teams and
+ * the region add those integers, and the region total is rounded to double
+ * once.  The result is the correctly rounded sum whatever the team, wave or
+ * launch layout.
  */
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -27,59 +32,19 @@
 using namespace dsr;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
 extern __shared__ __align__(16) uint8_t dsr_lds[];
 
-/* ---- 128/192-bit integer helpers --------------------------------------- */
-struct lane_acc {
-    uint64_t lo, hi;   /* signed 128-bit, two's complement */
-    uint32_t bad;      /* a value fell outside the exact-sum window */
-};
+/* Address-space qualifiers: loop buffers are global memory; without the
+ * qualifier the compiler emits flat instructions for them, which also wait
+ * on the LDS counter and cannot use scalar-base addressing. */
+#define GLB __attribute__((address_space(1)))
+#define LDSQ __attribute__((address_space(3)))
 
-__device__ __forceinline__ void acc_add_i64(lane_acc &a, int64_t v)
-{
-    uint64_t lo = (uint64_t)v, hi = (uint64_t)(v >> 63);
-    uint64_t n = a.lo + lo;
-    a.hi += hi + (n < a.lo);
-    a.lo = n;
-}
-
-/* Add y exactly, in units of 2^-75.  y = m * 2^(e-1075) with m the 53-bit
- * significand, so y / 2^-75 = m * 2^(e-1000). */
-__device__ __forceinline__ void acc_add_f64(lane_acc &a, double y)
-{
-    const uint64_t b = (uint64_t)__double_as_longlong(y);
-    const uint32_t e = (uint32_t)(b >> 52) & 0x7ffu;
-    const uint64_t frac = b & 0x000FFFFFFFFFFFFFull;
-    const uint64_t m = frac | (1ull << 52);
-    const int32_t s = (int32_t)e - 1000;
-    const uint32_t ns = (uint32_t)(-s);
-    const bool zero = (b << 1) == 0;
-    const bool ok = zero || (e <= 1054u &&
-                             (s >= 0 || (ns <= 52u && (m & ((1ull << ns) - 1ull)) == 0)));
-    a.bad |= (uint32_t)!ok;
-    uint64_t lo, hi;
-    if (s >= 0) {
-        const uint32_t sc = s > 54 ? 54u : (uint32_t)s;
-        lo = m << sc;
-        hi = sc ? (m >> (64u - sc)) : 0ull;
-    } else {
-        lo = m >> (ns & 63u);
-        hi = 0;
-    }
-    if (zero || !ok) { lo = 0; hi = 0; }
-    if (b >> 63) {
-        const uint64_t nlo = ~lo + 1ull;
-        hi = ~hi + (lo == 0 ? 1ull : 0ull);
-        lo = nlo;
-    }
-    const uint64_t n = a.lo + lo;
-    a.hi += hi + (n < a.lo);
-    a.lo = n;
-}
-
+/* ---- exact accumulation ------------------------------------------------ */
 struct i192 { uint64_t w0, w1, w2; };
 
 __device__ __forceinline__ i192 add192(i192 a, i192 b)
@@ -95,9 +60,96 @@ __device__ __forceinline__ i192 add192(i192 a, i192 b)
     return r;
 }
 
+__device__ __forceinline__ i192 from_i64(int64_t v)
+{
+    return i192{(uint64_t)v, (uint64_t)(v >> 63), (uint64_t)(v >> 63)};
+}
+
+/* v * 2^sh for a signed 64-bit v and 0 <= sh < 128. */
+__device__ __forceinline__ i192 shl192(int64_t v, int sh)
+{
+    const uint64_t ext = (uint64_t)(v >> 63);
+    uint64_t w0 = (uint64_t)v, w1 = ext, w2 = ext;
+    if (sh >= 64) { w2 = w1; w1 = w0; w0 = 0; sh -= 64; }
+    if (sh) {
+        w2 = (w2 << sh) | (w1 >> (64 - sh));
+        w1 = (w1 << sh) | (w0 >> (64 - sh));
+        w0 <<= sh;
+    }
+    return i192{w0, w1, w2};
+}
+
+struct lane_acc {
+    double b1, b2, b3;   /* bins on the 2^-5, 2^-40 and 2^-75 grids        */
+    int64_t i;           /* integer bodies: wrap-around int64 sum          */
+    uint32_t bad;        /* a value fell outside the exact-sum window      */
+    i192 big;            /* bins flushed so far, in 2^-75 units            */
+};
+
+__device__ __forceinline__ lane_acc acc_zero()
+{
+    lane_acc a;
+    a.b1 = a.b2 = a.b3 = 0.0;
+    a.i = 0;
+    a.bad = 0;
+    a.big = i192{0, 0, 0};
+    return a;
+}
+
+__device__ __forceinline__ void acc_add_i64(lane_acc &a, int64_t v)
+{
+    a.i = (int64_t)((uint64_t)a.i + (uint64_t)v);
+}
+
+/* Split y exactly into y = t1 + t2 + r2 with t1 on the 2^-5 grid, t2 on
+ * the 2^-40 grid and |r2| <= 2^-41, and add the parts to the bins.  r2 must
+ * itself be on the 2^-75 grid (checked by rounding it there). */
+__device__ __forceinline__ void acc_add_f64(lane_acc &a, double y)
+{
+    const double C1 = 0x1.8p47, C2 = 0x1.8p12, C3 = 0x1.8p-23;
+    const double t1 = (y + C1) - C1;
+    const double r1 = y - t1;
+    const double t2 = (r1 + C2) - C2;
+    const double r2 = r1 - t2;
+    const double t3 = (r2 + C3) - C3;
+    a.bad |= (uint32_t)((t3 != r2) | !(__builtin_fabs(y) < 0x1p32));
+    a.b1 += t1;
+    a.b2 += t2;
+    a.b3 += r2;
+}
+
+/* Bins of the same grid add exactly while each holds fewer than 2^16
+ * values. */
+__device__ __forceinline__ void acc_merge(lane_acc &a, const lane_acc &b)
+{
+    a.b1 += b.b1;
+    a.b2 += b.b2;
+    a.b3 += b.b3;
+    a.bad |= b.bad;
+}
+
+/* A lane's bins as one integer of 2^-75 units (bin values are integers of
+ * their grid below 2^53 in magnitude, so the conversions are exact). */
+__device__ __forceinline__ i192 bins_fixed(const lane_acc &a)
+{
+    const int64_t k1 = (int64_t)(a.b1 * 0x1p5);
+    const int64_t k2 = (int64_t)(a.b2 * 0x1p40);
+    const int64_t k3 = (int64_t)(a.b3 * 0x1p75);
+    i192 s = add192(shl192(k1, 70), shl192(k2, 35));
+    return add192(s, from_i64(k3));
+}
+
+/* Move the bins into the 192-bit accumulator (keeps them exact however
+ * many values a lane adds). */
+__device__ __forceinline__ void acc_flush(lane_acc &a)
+{
+    a.big = add192(a.big, bins_fixed(a));
+    a.b1 = a.b2 = a.b3 = 0.0;
+}
+
 __device__ __forceinline__ i192 widen(const lane_acc &a)
 {
-    return i192{a.lo, a.hi, (uint64_t)((int64_t)a.hi >> 63)};
+    return add192(add192(a.big, bins_fixed(a)), from_i64(a.i));
 }
 
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m)
@@ -173,20 +225,43 @@ __device__ double fixed_to_double(i192 v)
 }
 
 /* ---- loop bodies --------------------------------------------------------- */
-/* Lanes taking part in a body are numbered p in [0, P): worker waves first,
- * then the master wave if it joins.  Team range [lo, hi). */
+/* A span is a range [lo, hi) of loop iterations shared cyclically by P
+ * lanes, of which this lane is number p. */
 struct span_t {
     uint64_t lo, hi;
     uint32_t p, P;
 };
 
-__device__ __forceinline__ void body_affine_xor(const uint8_t *fb, const dsr_dloop &L,
-                                                span_t sp, lane_acc &A)
+/* Drive a body over this lane's static share `sp` and then, under the
+ * dynamic-tail schedule, over the blocks its wave claims from the loop's
+ * device counter (the next claim is issued before the current block runs,
+ * so its latency overlaps the work).  Claimed blocks are shared by the 64
+ * lanes of the claiming wave. */
+template <class F>
+__device__ __forceinline__ void for_spans(const dsr_dloop &L, span_t sp, uint32_t lane,
+                                          uint32_t *claim, lane_acc &A, F &&f)
 {
-    const int32_t *fr = (const int32_t *)(fb + 8);
-    const uint32_t a = (uint32_t)fr[0], b = (uint32_t)fr[1];
-    const uint32_t c = (uint32_t)fr[2], d = (uint32_t)fr[3];
-    int32_t *out = (int32_t *)L.out;
+    f(sp);
+    if (L.schedule != DSR_SCHED_DYNAMIC_TAIL) return;
+    uint32_t c = 0;
+    if (lane == 0) c = atomicAdd(claim, 1u);
+    c = (uint32_t)__shfl((int)c, 0, 64);
+    uint32_t since = 0;
+    for (;;) {
+        const uint64_t lo = L.dyn_start + (uint64_t)c * L.block;
+        if (lo >= L.n) break;
+        uint32_t cn = 0;
+        if (lane == 0) cn = atomicAdd(claim, 1u);
+        f(span_t{lo, min(L.n, lo + (uint64_t)L.block), lane, 64u});
+        /* a block adds at most 1024 values per lane: flush well before 2^16 */
+        if (++since == 16) { acc_flush(A); since = 0; }
+        c = (uint32_t)__shfl((int)cn, 0, 64);
+    }
+}
+
+__device__ __forceinline__ void affine_span(uint32_t a, uint32_t b, uint32_t c, uint32_t d,
+                                            GLB int32_t *out, span_t sp, lane_acc &A)
+{
     int64_t s = 0;
     for (uint64_t i = sp.lo + sp.p; i < sp.hi; i += sp.P) {
         const uint32_t ui = (uint32_t)i;
@@ -207,83 +282,116 @@ __device__ __forceinline__ double chain(const double (&s)[NI + NF], double xd)
     return acc;
 }
 
+/* Lane-to-element mapping of the streaming loop: a lane takes element
+ * pairs (8 B of x, 16 B of y), so every load instruction of a wave covers
+ * 512 contiguous bytes of x and every store 1 KB of y; consecutive batches
+ * of U pairs per lane are software-pipelined (the next batch's loads are in
+ * flight while the current batch computes). */
 template <int NI, int NF>
-__device__ __forceinline__ void body_fma_fixed(const uint8_t *fb, const dsr_dloop &L, span_t sp, lane_acc &A)
+__device__ __forceinline__ void fma_span(const double (&s)[NI + NF], const GLB float *__restrict__ x,
+                                         GLB double *__restrict__ y, span_t sp, lane_acc &A)
 {
-    double s[NI + NF];
-    const int32_t *si = (const int32_t *)(fb + 24 + 8 * NF);
-    const double *sf = (const double *)(fb + 24);
-#pragma unroll
-    for (int k = 0; k < NI; ++k) s[k] = (double)si[k];
-#pragma unroll
-    for (int k = 0; k < NF; ++k) s[NI + k] = sf[k];
-
-    const float *__restrict__ x = (const float *)L.in;
-    double *__restrict__ y = (double *)L.out;
-    const uint64_t vlo = min(sp.hi, (sp.lo + 3) & ~3ull);
-    const uint64_t vhi = max(vlo, sp.hi & ~3ull);
-    for (uint64_t i = sp.lo + sp.p; i < vlo; i += sp.P) {
-        const double v = chain<NI, NF>(s, (double)x[i]);
-        y[i] = v;
+    /* head element when the range starts on an odd index */
+    const uint64_t plo = min(sp.hi, (sp.lo + 1) & ~1ull);
+    const uint64_t phi = max(plo, sp.hi & ~1ull);
+    if (sp.lo < plo && sp.p == 0) {
+        const double v = chain<NI, NF>(s, (double)x[sp.lo]);
+        y[sp.lo] = v;
         acc_add_f64(A, v);
     }
-    const f32x4 *__restrict__ x4 = (const f32x4 *)x;
-    f64x2 *__restrict__ y2 = (f64x2 *)y;
-    const uint64_t nv1 = vhi >> 2;
-    uint64_t v = (vlo >> 2) + sp.p;
-    constexpr int U = (NI + NF >= 32) ? 2 : 4;
-    for (; v + (uint64_t)(U - 1) * sp.P < nv1; v += (uint64_t)U * sp.P) {
-        f32x4 xv[U];
+    lane_acc Ac[2] = {acc_zero(), acc_zero()};
+    const GLB f32x2 *__restrict__ x2 = (const GLB f32x2 *)x;
+    GLB f64x2 *__restrict__ y2 = (GLB f64x2 *)y;
+    const uint64_t nv1 = phi >> 1;
+    constexpr int U = (NI + NF >= 64) ? 4 : 8;
+    const uint64_t step = (uint64_t)U * sp.P;
+    uint64_t v = (plo >> 1) + sp.p;
+    if (v + (uint64_t)(U - 1) * sp.P < nv1) {
+        f32x2 cur[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = __builtin_nontemporal_load(&x4[v + (uint64_t)u * sp.P]);
+        for (int u = 0; u < U; ++u) cur[u] = __builtin_nontemporal_load(&x2[v + (uint64_t)u * sp.P]);
+        for (;;) {
+            const uint64_t vn = v + step;
+            const bool more = vn + (uint64_t)(U - 1) * sp.P < nv1;
+            f32x2 nxt[U];
+            if (more) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t w = v + (uint64_t)u * sp.P;
-            f64x2 lo2, hi2;
-            lo2.x = chain<NI, NF>(s, (double)xv[u].x);
-            lo2.y = chain<NI, NF>(s, (double)xv[u].y);
-            hi2.x = chain<NI, NF>(s, (double)xv[u].z);
-            hi2.y = chain<NI, NF>(s, (double)xv[u].w);
-            __builtin_nontemporal_store(lo2, &y2[2 * w]);
-            __builtin_nontemporal_store(hi2, &y2[2 * w + 1]);
-            acc_add_f64(A, lo2.x);
-            acc_add_f64(A, lo2.y);
-            acc_add_f64(A, hi2.x);
-            acc_add_f64(A, hi2.y);
+                for (int u = 0; u < U; ++u) nxt[u] = __builtin_nontemporal_load(&x2[vn + (uint64_t)u * sp.P]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                f64x2 r;
+                r.x = chain<NI, NF>(s, (double)cur[u].x);
+                r.y = chain<NI, NF>(s, (double)cur[u].y);
+                __builtin_nontemporal_store(r, &y2[v + (uint64_t)u * sp.P]);
+                acc_add_f64(Ac[0], r.x);
+                acc_add_f64(Ac[1], r.y);
+            }
+            v = vn;
+            if (!more) break;
+#pragma unroll
+            for (int u = 0; u < U; ++u) cur[u] = nxt[u];
         }
     }
     for (; v < nv1; v += sp.P) {
-        const f32x4 xv = __builtin_nontemporal_load(&x4[v]);
-        f64x2 lo2, hi2;
-        lo2.x = chain<NI, NF>(s, (double)xv.x);
-        lo2.y = chain<NI, NF>(s, (double)xv.y);
-        hi2.x = chain<NI, NF>(s, (double)xv.z);
-        hi2.y = chain<NI, NF>(s, (double)xv.w);
-        __builtin_nontemporal_store(lo2, &y2[2 * v]);
-        __builtin_nontemporal_store(hi2, &y2[2 * v + 1]);
-        acc_add_f64(A, lo2.x);
-        acc_add_f64(A, lo2.y);
-        acc_add_f64(A, hi2.x);
-        acc_add_f64(A, hi2.y);
+        const f32x2 xv = __builtin_nontemporal_load(&x2[v]);
+        f64x2 r;
+        r.x = chain<NI, NF>(s, (double)xv.x);
+        r.y = chain<NI, NF>(s, (double)xv.y);
+        __builtin_nontemporal_store(r, &y2[v]);
+        acc_add_f64(Ac[0], r.x);
+        acc_add_f64(Ac[1], r.y);
     }
-    for (uint64_t i = vhi + sp.p; i < sp.hi; i += sp.P) {
-        const double r = chain<NI, NF>(s, (double)x[i]);
-        y[i] = r;
+    if (phi < sp.hi && sp.p == 0) {
+        const double r = chain<NI, NF>(s, (double)x[phi]);
+        y[phi] = r;
         acc_add_f64(A, r);
     }
+    acc_merge(A, Ac[0]);
+    acc_merge(A, Ac[1]);
+}
+
+/* Shared scalars are wave-uniform: read them once as uniform values, so
+ * they live in scalar registers and no frame load is still in flight when
+ * the streaming loop starts (an outstanding frame load would make every
+ * iteration wait for all memory operations). */
+__device__ __forceinline__ uint32_t uniform_u32(const uint8_t *p)
+{
+    return uniform(*(const uint32_t *)p);
+}
+
+__device__ __forceinline__ double uniform_f64(const uint8_t *p)
+{
+    const uint64_t lo = uniform_u32(p), hi = uniform_u32(p + 4);
+    return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+
+template <int NI, int NF>
+__device__ __forceinline__ void body_fma_fixed(const uint8_t *fb, const dsr_dloop &L, span_t sp,
+                                               lane_acc &A, uint32_t *claim, uint32_t lane)
+{
+    double s[NI + NF];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) s[k] = (double)(int32_t)uniform_u32(fb + 24 + 8 * NF + 4 * k);
+#pragma unroll
+    for (int k = 0; k < NF; ++k) s[NI + k] = uniform_f64(fb + 24 + 8 * k);
+    const GLB float *x = (const GLB float *)L.in;
+    GLB double *y = (GLB double *)L.out;
+    for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_span<NI, NF>(s, x, y, q, A); });
 }
 
 /* fma chain with run-time scalar counts and an optional shared array:
  * the scalars are read from the frame (LDS broadcast or scalar-cache
  * loads) on every use. */
-__device__ __forceinline__ void body_fma_generic(const uint8_t *fb, const dsr_dloop &L, span_t sp, lane_acc &A)
+__device__ __forceinline__ void fma_generic_span(const uint8_t *fb, const dsr_dloop &L, span_t sp,
+                                                 lane_acc &A)
 {
     const uint32_t ni = L.ni, nf = L.nf, alen = L.alen;
     const double *sf = (const double *)(fb + 24);
     const int32_t *si = (const int32_t *)(fb + 24 + 8 * nf);
     const int32_t *arr = (const int32_t *)(fb + ((24 + 8 * nf + 4 * ni + 15) & ~15u));
-    const float *__restrict__ x = (const float *)L.in;
-    double *__restrict__ y = (double *)L.out;
+    const GLB float *__restrict__ x = (const GLB float *)L.in;
+    GLB double *__restrict__ y = (GLB double *)L.out;
     for (uint64_t i = sp.lo + sp.p; i < sp.hi; i += sp.P) {
         const double xd = (double)x[i];
         double acc = alen ? (double)arr[i % alen] : 0.0;
@@ -294,27 +402,31 @@ __device__ __forceinline__ void body_fma_generic(const uint8_t *fb, const dsr_dl
     }
 }
 
-/* Shared-array gather; arrays at `arr` (LDS or HBM), `len` elements each. */
-template <int NA>
-__device__ __forceinline__ i32x4 gather4(const int32_t *arr, uint32_t len, uint32_t na, uint32_t idx)
+/* Shared-array gather; arrays at `arr` (LDS or global pointer), `len`
+ * elements each. */
+__device__ __forceinline__ i32x4 load4(const LDSQ int32_t *p) { return *(const LDSQ i32x4 *)p; }
+__device__ __forceinline__ i32x4 load4(const GLB int32_t *p) { return *(const GLB i32x4 *)p; }
+
+template <int NA, class AP>
+__device__ __forceinline__ i32x4 gather4(AP arr, uint32_t len, uint32_t na, uint32_t idx)
 {
     i32x4 s = {0, 0, 0, 0};
     if (NA > 0) {
 #pragma unroll
-        for (int j = 0; j < NA; ++j) s += *(const i32x4 *)(arr + (uint64_t)j * len + idx);
+        for (int j = 0; j < NA; ++j) s += load4(arr + (uint64_t)j * len + idx);
     } else {
-        for (uint32_t j = 0; j < na; ++j) s += *(const i32x4 *)(arr + (uint64_t)j * len + idx);
+        for (uint32_t j = 0; j < na; ++j) s += load4(arr + (uint64_t)j * len + idx);
     }
     return s;
 }
 
 /* Vectors [v0, v1) of 4 elements, visited v0 + k*stride; len % 4 == 0. */
-template <int NA>
-__device__ __forceinline__ void gather_vectors(const int32_t *arr, const dsr_dloop &L,
-                                               uint64_t v0, uint64_t v1, uint64_t stride)
+template <int NA, class AP>
+__device__ __forceinline__ void gather_vectors(AP arr, const dsr_dloop &L, uint64_t v0, uint64_t v1,
+                                               uint64_t stride)
 {
     const uint32_t len = L.len;
-    i32x4 *__restrict__ out4 = (i32x4 *)L.out;
+    GLB i32x4 *__restrict__ out4 = (GLB i32x4 *)L.out;
     uint32_t idx = (uint32_t)((v0 * 4) % len);
     const uint32_t step = (uint32_t)((stride * 4) % len);
     for (uint64_t v = v0; v < v1; v += stride) {
@@ -327,10 +439,11 @@ __device__ __forceinline__ void gather_vectors(const int32_t *arr, const dsr_dlo
     }
 }
 
-__device__ __forceinline__ void gather_scalar(const int32_t *arr, const dsr_dloop &L,
-                                              uint64_t i0, uint64_t i1, uint64_t stride)
+template <class AP>
+__device__ __forceinline__ void gather_scalar(AP arr, const dsr_dloop &L, uint64_t i0, uint64_t i1,
+                                              uint64_t stride)
 {
-    int32_t *out = (int32_t *)L.out;
+    GLB int32_t *out = (GLB int32_t *)L.out;
     for (uint64_t i = i0; i < i1; i += stride) {
         uint32_t s = (uint32_t)i;
         const uint32_t k = (uint32_t)(i % L.len);
@@ -339,8 +452,8 @@ __device__ __forceinline__ void gather_scalar(const int32_t *arr, const dsr_dloo
     }
 }
 
-template <int NA>
-__device__ __forceinline__ void body_gather_flat(const int32_t *arr, const dsr_dloop &L, span_t sp)
+template <int NA, class AP>
+__device__ __forceinline__ void gather_span(AP arr, const dsr_dloop &L, span_t sp)
 {
     if ((L.len & 3u) || (sp.lo & 3u)) {
         gather_scalar(arr, L, sp.lo + sp.p, sp.hi, sp.P);
@@ -353,10 +466,10 @@ __device__ __forceinline__ void body_gather_flat(const int32_t *arr, const dsr_d
 
 /* Nested level: the outer member (this wave) pushes an inner frame on its
  * own sub-stack and hands it to its four 16-lane groups. */
-template <int NA>
-__device__ __forceinline__ void body_gather_nested(team_t &T, const int32_t *arr, frame_t outer,
-                                   const dsr_dloop &L, span_t sp, uint32_t member,
-                                   uint32_t members, uint32_t &inner_pushes)
+template <int NA, class AP>
+__device__ __forceinline__ void body_gather_nested(team_t &T, AP arr, frame_t outer, const dsr_dloop &L,
+                                                   span_t sp, uint32_t member, uint32_t members,
+                                                   uint32_t &inner_pushes)
 {
     const bool vec = !((L.len & 3u) || (sp.lo & 3u));
     const uint64_t units = vec ? ((sp.hi - sp.lo) >> 2) : (sp.hi - sp.lo);
@@ -403,54 +516,63 @@ __device__ __forceinline__ const uint8_t *frame_ptr(const team_t &T, frame_t f)
  * lane): run-time loop only.  Other lengths use the run-time loop. */
 template <int VARIANT>
 __device__ __forceinline__ void run_body(team_t &T, uint32_t body, frame_t f, const dsr_dloop &L, span_t sp,
-                         lane_acc &A, uint32_t member, uint32_t members, uint32_t &inner_pushes)
+                                         lane_acc &A, uint32_t *claim, uint32_t member,
+                                         uint32_t members, uint32_t &inner_pushes)
 {
+    const uint32_t lane = T.lane;
     switch (body) {
-    case DSR_BODY_AFFINE_XOR:
-        body_affine_xor(frame_ptr(T, f), L, sp, A);
+    case DSR_BODY_AFFINE_XOR: {
+        const uint8_t *fr = frame_ptr(T, f) + 8;
+        const uint32_t a = uniform_u32(fr), b = uniform_u32(fr + 4);
+        const uint32_t c = uniform_u32(fr + 8), d = uniform_u32(fr + 12);
+        GLB int32_t *out = (GLB int32_t *)L.out;
+        for_spans(L, sp, lane, claim, A, [&](span_t q) { affine_span(a, b, c, d, out, q, A); });
         break;
+    }
     case DSR_BODY_FMA_CHAIN: {
         const uint8_t *fb = frame_ptr(T, f);
         const uint32_t ni = L.ni, nf = L.nf;
         if (VARIANT >= 0 && L.alen == 0) {
-            if (ni == 1 && nf == 0) { body_fma_fixed<1, 0>(fb, L, sp, A); break; }
-            if (ni == 1 && nf == 1) { body_fma_fixed<1, 1>(fb, L, sp, A); break; }
-            if (ni == 2 && nf == 2) { body_fma_fixed<2, 2>(fb, L, sp, A); break; }
-            if (ni == 4 && nf == 4) { body_fma_fixed<4, 4>(fb, L, sp, A); break; }
-            if (ni == 8 && nf == 8) { body_fma_fixed<8, 8>(fb, L, sp, A); break; }
+            if (ni == 1 && nf == 0) { body_fma_fixed<1, 0>(fb, L, sp, A, claim, lane); break; }
+            if (ni == 1 && nf == 1) { body_fma_fixed<1, 1>(fb, L, sp, A, claim, lane); break; }
+            if (ni == 2 && nf == 2) { body_fma_fixed<2, 2>(fb, L, sp, A, claim, lane); break; }
+            if (ni == 4 && nf == 4) { body_fma_fixed<4, 4>(fb, L, sp, A, claim, lane); break; }
+            if (ni == 8 && nf == 8) { body_fma_fixed<8, 8>(fb, L, sp, A, claim, lane); break; }
             if constexpr (VARIANT >= 1)
-                if (ni == 16 && nf == 16) { body_fma_fixed<16, 16>(fb, L, sp, A); break; }
+                if (ni == 16 && nf == 16) { body_fma_fixed<16, 16>(fb, L, sp, A, claim, lane); break; }
             if constexpr (VARIANT >= 2)
-                if (ni == 32 && nf == 32) { body_fma_fixed<32, 32>(fb, L, sp, A); break; }
+                if (ni == 32 && nf == 32) { body_fma_fixed<32, 32>(fb, L, sp, A, claim, lane); break; }
         }
-        body_fma_generic(fb, L, sp, A);
+        for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_generic_span(fb, L, q, A); });
         break;
     }
     case DSR_BODY_GATHER: {
         if (f.space == SPACE_LDS) {
-            const int32_t *arr = (const int32_t *)(dsr_lds + cb_bytes(T.nw) + f.off);
+            const LDSQ int32_t *arr = (const LDSQ int32_t *)(dsr_lds + cb_bytes(T.nw) + f.off);
             switch (L.arrays) {
-            case 1: body_gather_flat<1>(arr, L, sp); break;
-            case 2: body_gather_flat<2>(arr, L, sp); break;
-            case 3: body_gather_flat<3>(arr, L, sp); break;
-            case 4: body_gather_flat<4>(arr, L, sp); break;
-            default: body_gather_flat<0>(arr, L, sp); break;
+#define GATHER_CASE(NA) for_spans(L, sp, lane, claim, A, [&](span_t q) { gather_span<NA>(arr, L, q); }); break;
+            case 1: GATHER_CASE(1)
+            case 2: GATHER_CASE(2)
+            case 3: GATHER_CASE(3)
+            case 4: GATHER_CASE(4)
+            default: GATHER_CASE(0)
             }
         } else {
-            const int32_t *arr = (const int32_t *)frame_hbm(T, f);
+            const GLB int32_t *arr = (const GLB int32_t *)frame_hbm(T, f);
             switch (L.arrays) {
-            case 1: body_gather_flat<1>(arr, L, sp); break;
-            case 2: body_gather_flat<2>(arr, L, sp); break;
-            case 3: body_gather_flat<3>(arr, L, sp); break;
-            case 4: body_gather_flat<4>(arr, L, sp); break;
-            default: body_gather_flat<0>(arr, L, sp); break;
+            case 1: GATHER_CASE(1)
+            case 2: GATHER_CASE(2)
+            case 3: GATHER_CASE(3)
+            case 4: GATHER_CASE(4)
+            default: GATHER_CASE(0)
+#undef GATHER_CASE
             }
         }
         break;
     }
     case DSR_BODY_GATHER_NESTED: {
         if (f.space == SPACE_LDS) {
-            const int32_t *arr = (const int32_t *)(dsr_lds + cb_bytes(T.nw) + f.off);
+            const LDSQ int32_t *arr = (const LDSQ int32_t *)(dsr_lds + cb_bytes(T.nw) + f.off);
             switch (L.arrays) {
             case 1: body_gather_nested<1>(T, arr, f, L, sp, member, members, inner_pushes); break;
             case 2: body_gather_nested<2>(T, arr, f, L, sp, member, members, inner_pushes); break;
@@ -459,7 +581,7 @@ __device__ __forceinline__ void run_body(team_t &T, uint32_t body, frame_t f, co
             default: body_gather_nested<0>(T, arr, f, L, sp, member, members, inner_pushes); break;
             }
         } else {
-            const int32_t *arr = (const int32_t *)frame_hbm(T, f);
+            const GLB int32_t *arr = (const GLB int32_t *)frame_hbm(T, f);
             switch (L.arrays) {
             case 1: body_gather_nested<1>(T, arr, f, L, sp, member, members, inner_pushes); break;
             case 2: body_gather_nested<2>(T, arr, f, L, sp, member, members, inner_pushes); break;
@@ -478,8 +600,8 @@ __device__ __forceinline__ void run_body(team_t &T, uint32_t body, frame_t f, co
 __device__ __forceinline__ span_t team_span(const dsr_dloop &L, uint32_t team, uint32_t p, uint32_t P)
 {
     span_t s;
-    s.lo = min(L.n, (uint64_t)team * L.chunk);
-    s.hi = min(L.n, s.lo + L.chunk);
+    s.lo = min(L.dyn_start, (uint64_t)team * L.chunk);
+    s.hi = min(L.dyn_start, s.lo + L.chunk);
     s.p = p;
     s.P = P;
     return s;
@@ -492,9 +614,12 @@ __device__ __forceinline__ void participate(team_t &T, const dsr_dregion &R, con
 {
     const uint32_t nwork = C.master_joins ? T.nw : T.nw - 1;
     const dsr_dloop &L = R.loops[loop];
-    lane_acc A{0, 0, 0};
-    run_body<VARIANT>(T, body, f, L, team_span(L, team, T.wave * 64 + T.lane, nwork * 64), A, T.wave,
-                      nwork, inner_pushes);
+    lane_acc A = acc_zero();
+    uint32_t *tr = C.trace ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
+    if (tr && T.lane == 0) tr[96 + 2 * T.wave] = (uint32_t)wall_clock64();
+    run_body<VARIANT>(T, body, f, L, team_span(L, team, T.wave * 64 + T.lane, nwork * 64), A,
+                      &R.result->claim[loop], T.wave, nwork, inner_pushes);
+    if (tr && T.lane == 0) tr[97 + 2 * T.wave] = (uint32_t)wall_clock64();
     const i192 w = wave_sum192(widen(A));
     const uint32_t bad = __any(A.bad != 0);
     end_parallel(T, w.w0, w.w1, w.w2, bad);
@@ -530,9 +655,11 @@ __device__ __forceinline__ void master_program(team_t &T, const dsr_dregion &R, 
 {
     cb_header *h = header(T);
     uint32_t *tr = C.trace ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
+    if (tr && T.lane == 0) tr[86] = (uint32_t)wall_clock64();
     wave_sync();
     int32_t err = 0;
     uint32_t npush = 0;
+    bool stamped = false;
     const uint32_t nwork = C.master_joins ? T.nw : T.nw - 1;
     for (uint32_t k = 0; k < R.n_ops; ++k) {
         const dsr_op op = R.ops[k];
@@ -555,12 +682,23 @@ __device__ __forceinline__ void master_program(team_t &T, const dsr_dregion &R, 
             f.size = uniform(ft[2]);
             publish(T, f, op.body, op.loop);
             barriers++;
+            if (tr && T.lane == 0 && !stamped) {
+                const uint64_t t0 = wall_clock64();
+                tr[82] = (uint32_t)t0;
+                tr[83] = (uint32_t)(t0 >> 32);
+            }
+            stamped = true;
             if (C.master_joins) {
                 participate<VARIANT>(T, R, C, team, op.body, f, op.loop, inner_pushes);
             } else {
                 end_parallel(T, 0, 0, 0, 0);
             }
             barriers++;
+            if (tr && T.lane == 0) {
+                const uint64_t t1 = wall_clock64();
+                tr[84] = (uint32_t)t1;
+                tr[85] = (uint32_t)(t1 >> 32);
+            }
             /* join done: combine the participating waves' partials */
             i192 tot{0, 0, 0};
             for (uint32_t w = 0; w < T.nw; ++w) {
@@ -650,6 +788,7 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t lane)
     if (prev == R.teams - 1) {
         __threadfence();
         combine_teams(R, lane);
+        if (lane < DSR_MAX_LOOPS) R.result->claim[lane] = 0;
         if (lane == 0) {
             R.result->final_error = atomicExch(&R.result->error, 0);
             R.result->done += 1;

@@ -36,8 +36,12 @@ DSR_BODY_FMA_CHAIN = 2
 DSR_BODY_GATHER = 3
 DSR_BODY_GATHER_NESTED = 4
 
+DSR_SCHED_STATIC = 0
+DSR_SCHED_DYNAMIC_TAIL = 1
+
 DSR_F_TRACE = 1
-DSR_TRACE_WORDS = 96
+DSR_F_TIMING = 2
+DSR_TRACE_WORDS = 128
 
 # the exported C entry points (include/dsr.h)
 EXPORTS = ("dsr_init", "dsr_destroy", "dsr_region_begin", "dsr_push", "dsr_publish",
@@ -56,7 +60,7 @@ class dsr_loop(C.Structure):
     _fields_ = [("n", C.c_uint64), ("chunk", C.c_uint64), ("in_", C.c_void_p),
                 ("out", C.c_void_p), ("ni", C.c_uint32), ("nf", C.c_uint32),
                 ("alen", C.c_uint32), ("arrays", C.c_uint32), ("len", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("schedule", C.c_uint32), ("tail_pct", C.c_uint32), ("block", C.c_uint32)]
 
 
 class DsrError(RuntimeError):
@@ -153,8 +157,9 @@ def dsr_push(region, nbytes, init=b"", init_stride=0, init_bytes=None):
 
 
 def dsr_publish(region, frame, body, n, inp=0, out=0, chunk=0, ni=0, nf=0, alen=0, arrays=0,
-                length=0):
-    L = dsr_loop(n, chunk, inp or None, out or None, ni, nf, alen, arrays, length, 0)
+                length=0, schedule=0, tail_pct=0, block=0):
+    L = dsr_loop(n, chunk, inp or None, out or None, ni, nf, alen, arrays, length, schedule,
+                 tail_pct, block)
     return _check(lib().dsr_publish(region, frame, body, C.byref(L)), "dsr_publish")
 
 
@@ -195,7 +200,9 @@ def dsr_region_trace(region, team):
     return {"placements": [(("lds", "hbm")[t[1 + 3 * p]], t[2 + 3 * p], t[3 + 3 * p])
                            for p in range(min(k, 16))],
             "barriers": t[49:65], "inner_pushes": t[65:81],
-            "error": C.c_int32(t[81]).value}
+            "error": C.c_int32(t[81]).value,
+            "t_start": t[82] | (t[83] << 32), "t_end": t[84] | (t[85] << 32),
+            "t_team": t[86], "wave_loop": [(t[96 + 2 * w], t[97 + 2 * w]) for w in range(16)]}
 
 
 def dsr_region_elapsed(region):

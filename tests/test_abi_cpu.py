@@ -39,7 +39,8 @@ def test_bad_configs():
     for kw, code in [({"wg_size": 100}, D.DSR_E_INVAL), ({"wg_size": 2048}, D.DSR_E_INVAL),
                      ({"max_teams": 0}, D.DSR_E_INVAL), ({"lds_slab_bytes": 20}, D.DSR_E_INVAL),
                      ({"lds_slab_bytes": 160 * 1024}, D.DSR_E_LDS),
-                     ({"hbm_slab_bytes": 17}, D.DSR_E_INVAL), ({"flags": 8}, D.DSR_E_INVAL)]:
+                     ({"hbm_slab_bytes": 17}, D.DSR_E_INVAL), ({"flags": 8}, D.DSR_E_INVAL),
+                     ({"flags": 4}, D.DSR_E_INVAL)]:
         with pytest.raises(D.DsrError) as e:
             host_ctx(**kw)
         assert e.value.code == code, kw
@@ -127,5 +128,27 @@ def test_region_limits():
     with pytest.raises(D.DsrError) as e:
         D.dsr_pop(r, 0)
     assert e.value.code == D.DSR_E_UNDERFLOW
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+
+
+def test_dynamic_tail_validation():
+    ctx = host_ctx()
+    r = D.dsr_region_begin(ctx, 4)
+    f = D.dsr_push(r, 64)
+    g = D.dsr_push(r, 64, bytes(64 * 4), init_stride=64)      # per-team frame copies
+    bad = [dict(frame=f, chunk=128), dict(frame=f, block=100), dict(frame=f, block=1 << 17),
+           dict(frame=f, tail_pct=100), dict(frame=g), dict(frame=f, body=D.DSR_BODY_GATHER_NESTED)]
+    for kw in bad:
+        frame = kw.pop("frame")
+        body = kw.pop("body", D.DSR_BODY_GATHER)
+        with pytest.raises(D.DsrError) as e:
+            D.dsr_publish(r, frame, body, 1000, out=0x1000, arrays=1, length=4, schedule=1, **kw)
+        assert e.value.code == D.DSR_E_INVAL, kw
+    D.dsr_publish(r, f, D.DSR_BODY_GATHER, 1000, out=0x1000, arrays=1, length=4, schedule=1)
+    with pytest.raises(D.DsrError):
+        D.dsr_publish(r, f, D.DSR_BODY_GATHER, 1000, out=0x1000, arrays=1, length=4, schedule=2)
+    D.dsr_pop(r, g)
+    D.dsr_pop(r, f)
     D.dsr_region_free(r)
     D.dsr_destroy(ctx)

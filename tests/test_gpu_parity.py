@@ -124,14 +124,14 @@ def test_cfg1_each_team_reads_its_own_frame():
 
 
 # ---- Figure 5 pattern: K shared scalars, fma chain, exact reduction ---------
-def fma_region(ctx, teams, s_i32, s_f64, x, y, arr=None, chunk=0):
+def fma_region(ctx, teams, s_i32, s_f64, x, y, arr=None, chunk=0, schedule=0, tail_pct=0, block=0):
     img, size = D.fma_chain_frame(s_i32, s_f64, arr)
 
     def build(r):
         f = D.dsr_push(r, size, img)
         D.dsr_publish(r, f, D.DSR_BODY_FMA_CHAIN, x.numel(), inp=x.data_ptr(), out=y.data_ptr(),
                       ni=len(s_i32), nf=len(s_f64), alen=0 if arr is None else len(arr),
-                      chunk=chunk)
+                      chunk=chunk, schedule=schedule, tail_pct=tail_pct, block=block)
         D.dsr_pop(r, f)
     return run_region(ctx, teams, build)
 
@@ -162,16 +162,98 @@ def test_cfg2_scalar_sweep_small(K, wg, joins):
 
 
 @pytest.mark.parametrize("K", W.CFG2_KS)
-def test_cfg2_full_size(K):
-    """512 teams x 256 threads over 2**24 elements: the benchmarked shape."""
-    say("cfg2 full K", K)
+@pytest.mark.parametrize("schedule", [D.DSR_SCHED_STATIC, D.DSR_SCHED_DYNAMIC_TAIL])
+def test_cfg2_full_size(K, schedule):
+    """512 teams x 256 threads over 2**24 elements: the benchmarked shape,
+    launched twice (the dynamic-tail counters reset between launches)."""
+    say("cfg2 full K", K, "schedule", schedule)
     cf, x_np = W.cfg2_inputs(K)
     ctx = D.dsr_init(wg_size=256, lds_slab_bytes=4096, max_teams=512)
     x = torch.from_numpy(x_np).cuda()
     y = torch.zeros(x.numel(), dtype=torch.float64, device="cuda")
-    st, r = fma_region(ctx, 512, cf.s_i32, cf.s_f64, x, y)
+    st, r = fma_region(ctx, 512, cf.s_i32, cf.s_f64, x, y, schedule=schedule)
     assert st == 0
     check_fma(r, x_np, cf.s_i32, cf.s_f64, y)
+    y.zero_()
+    D.dsr_launch(r, stream())
+    assert D.dsr_region_sync(r) == 0
+    check_fma(r, x_np, cf.s_i32, cf.s_f64, y)
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+
+
+@pytest.mark.parametrize("K", [1, 8, 64])
+@pytest.mark.parametrize("tail_pct,block,joins", [(25, 1024, 0), (99, 128, 1), (50, 65536, 0),
+                                                  (10, 384, 1)])
+def test_cfg2_dynamic_tail_small(K, tail_pct, block, joins):
+    say("cfg2 dynamic K", K, tail_pct, block, joins)
+    n = 200003
+    cf, x_np = W.cfg2_inputs(K, n=n)
+    ctx = D.dsr_init(wg_size=256, lds_slab_bytes=4096, max_teams=64, master_joins=joins)
+    x = torch.from_numpy(x_np).cuda()
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, r = fma_region(ctx, 9, cf.s_i32, cf.s_f64, x, y, schedule=1, tail_pct=tail_pct, block=block)
+    assert st == 0
+    check_fma(r, x_np, cf.s_i32, cf.s_f64, y)
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+
+
+def test_dynamic_tail_many_blocks_per_lane():
+    """A single team claims every block of a long tail: each lane adds far
+    more than 2**16 values, which the bins only hold exactly because the
+    claimed blocks flush them."""
+    say("dynamic tail long")
+    n = 1 << 23
+    cf, x_np = W.cfg2_inputs(8, n=n)
+    ctx = D.dsr_init(wg_size=64, lds_slab_bytes=4096, max_teams=4)
+    x = torch.from_numpy(x_np).cuda()
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, r = fma_region(ctx, 1, cf.s_i32, cf.s_f64, x, y, schedule=1, tail_pct=99, block=65536)
+    assert st == 0
+    check_fma(r, x_np, cf.s_i32, cf.s_f64, y)
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+
+
+@pytest.mark.parametrize("A,length,hbm_only", [(1, 16, 0), (4, 4096, 0), (2, 16384, 1), (3, 100, 0)])
+def test_gather_dynamic_tail(A, length, hbm_only):
+    say("gather dynamic", A, length, hbm_only)
+    arrs = W.cfg3_arrays(A, length)
+    n = (1 << 18) + 5
+    frame = 4 * A * length
+    ctx = D.dsr_init(wg_size=256, lds_slab_bytes=0 if hbm_only else LDS_MAX4,
+                     hbm_slab_bytes=(frame + 15) // 16 * 16, max_teams=16)
+    out = t_i32(n)
+
+    def build(r):
+        f = D.dsr_push(r, frame, D.gather_frame(arrs))
+        D.dsr_publish(r, f, D.DSR_BODY_GATHER, n, out=out.data_ptr(), arrays=A, length=length,
+                      schedule=1, tail_pct=40, block=512)
+        D.dsr_pop(r, f)
+    st, r = run_region(ctx, 16, build)
+    assert st == 0
+    assert np.array_equal(out.cpu().numpy(), R.gather(arrs, 0, n))
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+
+
+def test_affine_dynamic_tail():
+    say("affine dynamic")
+    c = W.cfg1_inputs()
+    ctx = D.dsr_init(wg_size=256, lds_slab_bytes=4096, max_teams=4)
+    n = 100000
+    out = t_i32(n)
+
+    def build(r):
+        f = D.dsr_push(r, 24, D.affine_xor_frame(c.a, c.b, c.c, c.d))
+        D.dsr_publish(r, f, D.DSR_BODY_AFFINE_XOR, n, out=out.data_ptr(), schedule=1,
+                      tail_pct=60, block=256)
+        D.dsr_pop(r, f)
+    st, r = run_region(ctx, 4, build)
+    assert st == 0
+    ro, rs = R.affine_xor(c.a, c.b, c.c, c.d, 0, n)
+    assert np.array_equal(out.cpu().numpy(), ro) and D.dsr_region_reduction(r, 0)[0] == rs
     D.dsr_region_free(r)
     D.dsr_destroy(ctx)
 
