@@ -222,6 +222,167 @@ int dsr_region_elapsed(dsr_region *r, float *ms);
 /* Release a region's host and device memory (syncs its last launch). */
 int dsr_region_free(dsr_region *r);
 
+/* ---- batched form ---------------------------------------------------------
+ * Many regions run in one persistent launch: workgroups stay resident and
+ * their master waves claim (region, team) items from a device counter,
+ * largest per-team work first, running each region's program as that team;
+ * worker waves stay in the await loop across items (the paper's dynamic
+ * work allocation, section 4, applied across regions).  The last team of a
+ * region combines its reductions and stamps the region's completion time.
+ * Results equal those of launching every region alone.  */
+typedef struct dsr_batch dsr_batch;
+
+typedef struct dsr_tune {
+    uint32_t wg_size;            /* threads per workgroup (multiple of 64, 64..1024) */
+    uint32_t lds_slab_bytes;     /* LDS stack per workgroup                        */
+    uint32_t overflow_threshold; /* frames above this go to HBM (0 = no limit)     */
+    uint32_t master_joins;       /* master wave runs iterations too                */
+    uint32_t grid;               /* persistent workgroups (0 = as many as fit)     */
+    uint32_t use_graph;          /* 1: capture the launch in a hipGraph once and
+                                    replay it                                       */
+} dsr_tune;
+
+/* Pack `n` finished regions of context `ctx` (every frame popped) into a
+ * batch: their programs, loop descriptors, initial frame bytes, partial
+ * sums and results are copied into a few device arenas once.  The regions
+ * may be freed afterwards.  The tune starts as the context's configuration. */
+int dsr_batch_create(dsr_ctx *ctx, dsr_region *const *regions, int32_t n, dsr_batch **out);
+
+/* Set the launch configuration (DSR_E_LDS / DSR_E_INVAL as for dsr_init;
+ * DSR_E_NOMEM if `grid` exceeds the context's HBM slab slots). */
+int dsr_batch_tune(dsr_batch *b, const dsr_tune *tune);
+
+/* The tune in effect, with `grid` resolved to the workgroup count used. */
+int dsr_batch_get_tune(dsr_batch *b, dsr_tune *out);
+
+/* Run every region of the batch in one persistent launch on `stream`
+ * (hipStream_t as void*; with use_graph the launch is a graph replay). */
+int dsr_batch_launch(dsr_batch *b, void *stream);
+
+/* Run the same regions with one kernel launch per region, in order, on
+ * `stream` (the comparison form). */
+int dsr_batch_launch_each(dsr_batch *b, void *stream);
+
+/* Wait for the batch's last launch; returns the first region error or 0. */
+int dsr_batch_sync(dsr_batch *b);
+
+/* Reduction `index` of region `r` from the last launch (after sync), as
+ * dsr_region_reduction; *status receives the region's error code. */
+int dsr_batch_result(dsr_batch *b, int32_t r, int32_t index, int64_t *i64, double *f64,
+                     uint64_t *fixed3, int32_t *status);
+
+/* Completion times of the last persistent launch in microseconds after its
+ * first item was claimed (from the device's 100 MHz clock): us[r] for
+ * region r.  For dsr_batch_launch_each these are not recorded (DSR_E_STATE). */
+int dsr_batch_times(dsr_batch *b, double *us, int32_t n);
+
+/* Duration of the last launch (either form) in milliseconds, from HIP
+ * events around it. */
+int dsr_batch_elapsed(dsr_batch *b, float *ms);
+
+int dsr_batch_free(dsr_batch *b);
+
+/* Autotuner: time `reps` persistent launches of the batch under each of
+ * the `n_cand` candidate tunes (candidates that do not fit the device are
+ * skipped), leave the fastest in effect, and return it in *best and every
+ * candidate's mean milliseconds in ms[i] (negative if skipped). */
+int dsr_autotune(dsr_batch *b, const dsr_tune *cand, int32_t n_cand, int32_t reps, void *stream,
+                 dsr_tune *best, float *ms);
+
+/* ---- served form ----------------------------------------------------------
+ * A resident server kernel runs region requests as they arrive.  The host
+ * submits a request (a finished region used as a program template) into a
+ * free slot: its program, loop descriptors and frame images are copied into
+ * the slot's host-coherent arena, its teams become items in a ring, and the
+ * published count is advanced.  Persistent workgroups claim items as they
+ * are published, so requests that arrive while others run overlap on the
+ * device (continuous batching).  The last team of a request writes a
+ * completion record that the host polls.
+ *
+ * Admission: a request is rejected with DSR_E_NOMEM if one of its teams'
+ * frames fits neither the LDS stack nor the HBM slot of a server team (the
+ * same rule the device applies), and deferred with DSR_E_BUSY while no slot
+ * is free or while the LDS or HBM bytes of the admitted, unfinished
+ * requests' team stacks would exceed the server's budget (the resident
+ * teams' LDS slabs and HBM slots).  Budgets are returned on completion.
+ *
+ * The server kernel leaves when dsr_serve_stop is called, or by itself
+ * after `idle_ms` without new work; from then on dsr_serve_submit fails
+ * with DSR_E_STATE.  A device-wide synchronisation (hipDeviceSynchronize)
+ * waits for the resident server kernel, i.e. until it leaves. */
+typedef struct dsr_server dsr_server;
+
+typedef struct dsr_serve_cfg {
+    dsr_tune tune;            /* resident workgroups (grid 0 = as many as fit)   */
+    uint32_t slots;           /* requests in flight at most                      */
+    uint32_t slot_bytes;      /* frame-image bytes per slot                      */
+    uint32_t max_teams;       /* teams per request at most                       */
+    uint32_t ring_items;      /* item ring capacity (power of two)               */
+    uint32_t idle_ms;         /* server exits after this long without new work  */
+    uint32_t budget_pct;      /* admission budget, percent of the resident stacks
+                                 (0 = 100)                                        */
+} dsr_serve_cfg;
+
+typedef struct dsr_done {
+    uint64_t ticket;
+    int32_t status;           /* DSR_OK, DSR_E_NOMEM or DSR_E_RANGE              */
+    int32_t n_red;
+    double f64[8];            /* reductions in publish order                     */
+    int64_t i64[8];
+    uint64_t fixed[8][3];
+    double device_us;         /* device completion time, microseconds on the
+                                 device clock since the server started           */
+} dsr_done;
+
+/* Launch the server kernel on its own stream.  Regions submitted later must
+ * belong to `ctx` and use one of the bodies compiled into the server (all
+ * bodies; fixed-length fma chains up to 8+8 scalars, longer ones through the
+ * run-time loop). */
+int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_server **out);
+
+/* Submit region `program` (not launched itself; its frames all popped).
+ * `outs` (may be NULL) replaces the output pointer of each of its loops,
+ * so one template can serve many requests with separate output buffers.
+ * *ticket identifies the request in dsr_serve_poll.  The server runs on a
+ * stream of its own and may start the request at once: its input and
+ * output buffers must be ready (any work producing or clearing them
+ * finished) when this is called. */
+int dsr_serve_submit(dsr_server *s, dsr_region *program, void *const *outs, int32_t n_outs,
+                     uint64_t *ticket);
+
+/* Collect up to `max` completed requests (never blocks); returns how many
+ * were written to `out`, or a negative error. */
+int dsr_serve_poll(dsr_server *s, dsr_done *out, int32_t max);
+
+/* Requests submitted and not yet collected by dsr_serve_poll. */
+int dsr_serve_pending(dsr_server *s);
+
+/* Replay an open-loop arrival schedule against the server from the calling
+ * thread: request q (program programs[prog[q]]) arrives arrival_s[q] seconds
+ * after the call (non-decreasing).  Requests are submitted in arrival
+ * order as soon as they have arrived and are admitted (a deferred request
+ * holds back the ones behind it); each writes its loops' outputs to
+ * slot_outs[slot * n_loops_max + i] of the slot it was admitted into.  On
+ * return latency_us[q] is its time from arrival to the host observing its
+ * completion and done[q] its result.  Fails with DSR_E_BUSY if the
+ * schedule has not finished `timeout_s` seconds after its last arrival. */
+int dsr_serve_replay(dsr_server *s, dsr_region *const *programs, const int32_t *prog,
+                     const double *arrival_s, int32_t n, void *const *slot_outs,
+                     int32_t n_loops_max, double timeout_s, double *latency_us, dsr_done *done);
+
+/* The comparison form: the same schedule served by one kernel launch per
+ * request (batch region prog[q]) followed by a stream synchronisation, on
+ * one stream; a request that arrives while another runs waits for it.
+ * latency_us[q] is arrival to the end of its synchronisation; results are
+ * read with dsr_batch_result after the call (they hold each region's last
+ * run). */
+int dsr_batch_replay_serial(dsr_batch *b, const int32_t *prog, const double *arrival_s, int32_t n,
+                            double *latency_us);
+
+/* Stop the server: the kernel drains the published items and exits; then
+ * frees the server.  Completed requests not yet polled are dropped. */
+int dsr_serve_stop(dsr_server *s);
+
 /* Static string for a DSR_* code. */
 const char *dsr_strerror(int code);
 

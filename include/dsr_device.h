@@ -62,7 +62,9 @@ struct cb_header {
     uint32_t nframes;  /* live frames                              */
     int32_t error;     /* team error (DSR_E_* or 0)                */
     uint32_t bad;      /* OR of the workers' range flags           */
-    uint32_t pad[6];
+    uint32_t region;   /* launch-specific context published with the */
+    uint32_t team;     /* body: which region and which of its teams  */
+    uint32_t pad[4];
 };
 
 /* Bytes of control block for a team of nw waves. */
@@ -130,6 +132,22 @@ __device__ inline team_t team_init(uint8_t *lds, uint32_t nw, uint32_t lds_cap,
         h->bad = 0;
     }
     return T;
+}
+
+/* Master wave: empty the stack before a new region program (a persistent
+ * team runs many regions one after another). */
+__device__ inline void team_reset(team_t &T)
+{
+    wave_sync();
+    if (T.lane == 0) {
+        cb_header *h = header(T);
+        h->sp_lds = 0;
+        h->sp_hbm = 0;
+        h->nframes = 0;
+        h->error = 0;
+        h->bad = 0;
+    }
+    wave_sync();
 }
 
 /* Master wave: place a frame of nbytes (rounded up to 16).  LDS when it

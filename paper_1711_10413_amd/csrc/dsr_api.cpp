@@ -13,6 +13,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -55,6 +56,7 @@ struct dsr_region {
     uint64_t *d_partials;
     dsr_dresult *d_result;
     uint32_t *d_trace;
+    dsr_dregion *d_self;                /* this region's descriptor on the device */
     hipEvent_t ev0, ev1;
     bool timed;                         /* ev0 was recorded by the last launch */
     bool launched;
@@ -152,6 +154,7 @@ extern "C" int dsr_region_begin(dsr_ctx *ctx, int32_t teams, dsr_region **out)
     r->d_partials = nullptr;
     r->d_result = nullptr;
     r->d_trace = nullptr;
+    r->d_self = nullptr;
     r->ev0 = r->ev1 = nullptr;
     r->timed = false;
     r->launched = false;
@@ -354,7 +357,36 @@ static int upload(dsr_region *r)
     if ((rc = hip_ok(hipMemset(r->d_partials, 0, part_b)))) return rc;
     if ((rc = hip_ok(hipEventCreate(&r->ev0)))) return rc;
     if ((rc = hip_ok(hipEventCreate(&r->ev1)))) return rc;
+    dsr_dregion R{};
+    R.ops = r->d_ops;
+    R.loops = r->d_loops;
+    R.init = r->d_init;
+    R.partials = r->d_partials;
+    R.result = r->d_result;
+    R.trace = r->d_trace;
+    R.n_ops = (uint32_t)r->ops.size();
+    R.teams = (uint32_t)r->teams;
+    R.n_red = r->n_red;
+    R.red_kind_mask = r->red_kind_mask;
+    R.n_loops = (uint32_t)r->loops.size();
+    if (hipMalloc((void **)&r->d_self, sizeof(dsr_dregion)) != hipSuccess) return DSR_E_NOMEM;
+    if ((rc = hip_ok(hipMemcpy(r->d_self, &R, sizeof(R), hipMemcpyHostToDevice)))) return rc;
     return DSR_OK;
+}
+
+static dsr_dconfig make_dconfig(const dsr_ctx *c, uint32_t wg, uint32_t lds_slab, uint32_t threshold,
+                                uint32_t joins, uint32_t trace)
+{
+    dsr_dconfig C{};
+    C.serve = 0;
+    C.hbm_base = c->hbm;
+    C.hbm_slot_bytes = c->cfg.hbm_slab_bytes;
+    C.nw = wg / 64;
+    C.lds_cap = lds_slab;
+    C.threshold = threshold ? threshold : 0xFFFFFFFFu;
+    C.master_joins = (joins || C.nw == 1) ? 1u : 0u;
+    C.trace = trace;
+    return C;
 }
 
 extern "C" int dsr_launch(dsr_region *r, void *stream)
@@ -370,28 +402,16 @@ extern "C" int dsr_launch(dsr_region *r, void *stream)
         r->frozen = true;
     }
     hipStream_t s = (hipStream_t)stream;
-    dsr_dregion R{};
-    R.ops = r->d_ops;
-    R.loops = r->d_loops;
-    R.init = r->d_init;
-    R.partials = r->d_partials;
-    R.result = r->d_result;
-    R.trace = r->d_trace;
-    R.n_ops = (uint32_t)r->ops.size();
-    R.teams = (uint32_t)r->teams;
-    R.n_red = r->n_red;
-    R.red_kind_mask = r->red_kind_mask;
-    dsr_dconfig C{};
-    C.hbm_base = c->hbm;
-    C.hbm_slot_bytes = c->cfg.hbm_slab_bytes;
-    C.nw = c->nw;
-    C.lds_cap = c->cfg.lds_slab_bytes;
-    C.threshold = c->threshold;
-    C.master_joins = c->cfg.master_joins ? 1u : 0u;
-    C.trace = (c->cfg.flags & DSR_F_TRACE) ? 1u : 0u;
+    dsr_dlaunch LP{};
+    LP.regions = r->d_self;
+    LP.items = nullptr;
+    LP.n_regions = 1;
+    const dsr_dconfig C = make_dconfig(c, c->cfg.wg_size, c->cfg.lds_slab_bytes, c->cfg.overflow_threshold,
+                                       c->cfg.master_joins, (c->cfg.flags & DSR_F_TRACE) ? 1u : 0u);
     const bool timing = (c->cfg.flags & DSR_F_TIMING) != 0;
     if (timing && hipEventRecord(r->ev0, s) != hipSuccess) return DSR_E_HIP;
-    if (dsr_launch_region_kernel(&R, &C, c->cfg.wg_size, c->lds_bytes, r->variant, stream) != 0)
+    if (dsr_launch_region_kernel(&LP, &C, (uint32_t)r->teams, c->cfg.wg_size, c->lds_bytes, r->variant,
+                                 stream) != 0)
         return DSR_E_HIP;
     if (hipEventRecord(r->ev1, s) != hipSuccess) return DSR_E_HIP;
     r->timed = timing;
@@ -454,8 +474,814 @@ extern "C" int dsr_region_free(dsr_region *r)
     if (r->d_partials) hipFree(r->d_partials);
     if (r->d_result) hipFree(r->d_result);
     if (r->d_trace) hipFree(r->d_trace);
+    if (r->d_self) hipFree(r->d_self);
     if (r->ev0) hipEventDestroy(r->ev0);
     if (r->ev1) hipEventDestroy(r->ev1);
     delete r;
     return DSR_OK;
+}
+
+/* ---- batched form ---------------------------------------------------------- */
+struct dsr_batch {
+    dsr_ctx *ctx;
+    int32_t n;
+    uint8_t *d_arena;
+    dsr_dregion *d_regions;
+    dsr_dresult *d_results;
+    uint32_t *d_items;
+    uint32_t n_items;
+    uint32_t *d_counter;
+    uint64_t *d_done;
+    std::vector<int32_t> teams;
+    std::vector<uint32_t> n_red;
+    std::vector<std::vector<dsr_dloop>> loops;   /* host copies, for tune checks */
+    std::vector<dsr_dresult> h_results;
+    bool have_results;
+    uint32_t variant;
+    dsr_tune tune;
+    uint32_t grid;
+    uint32_t lds_bytes;
+    uint32_t lds_max;
+    uint32_t cus;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    hipStream_t own_stream;
+    hipEvent_t ev0, ev1;
+    int last;                                    /* 1 persistent, 2 one per region */
+};
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+extern "C" int dsr_batch_create(dsr_ctx *ctx, dsr_region *const *regions, int32_t n, dsr_batch **out)
+{
+    if (!ctx || !regions || !out || n < 1) return DSR_E_INVAL;
+    *out = nullptr;
+    if (ctx->device < 0) return DSR_E_STATE;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!regions[i] || regions[i]->ctx != ctx) return DSR_E_INVAL;
+        if (!regions[i]->live.empty()) return DSR_E_LIVE;
+    }
+    /* arena layout */
+    size_t off_ops = 0, sz = 0;
+    std::vector<size_t> o_ops(n), o_loops(n), o_init(n), o_part(n);
+    for (int32_t i = 0; i < n; ++i) { o_ops[i] = sz; sz += regions[i]->ops.size() * sizeof(dsr_op); }
+    sz = align256(sz);
+    for (int32_t i = 0; i < n; ++i) { o_loops[i] = sz; sz += regions[i]->loops.size() * sizeof(dsr_dloop); }
+    sz = align256(sz);
+    for (int32_t i = 0; i < n; ++i) { o_init[i] = sz; sz += (regions[i]->init.size() + 15) & ~(size_t)15; }
+    sz = align256(sz);
+    for (int32_t i = 0; i < n; ++i) {
+        o_part[i] = sz;
+        sz += (size_t)(regions[i]->n_red ? regions[i]->n_red : 1) * regions[i]->teams * 3 * sizeof(uint64_t);
+    }
+    sz = align256(sz);
+    const size_t o_res = sz;
+    sz = align256(sz + (size_t)n * sizeof(dsr_dresult));
+    const size_t o_reg = sz;
+    sz = align256(sz + (size_t)n * sizeof(dsr_dregion));
+    /* items: (region, team), largest per-team work first */
+    struct item { uint64_t work; uint32_t r, t; };
+    std::vector<item> items;
+    for (int32_t i = 0; i < n; ++i) {
+        const dsr_region *r = regions[i];
+        for (int32_t t = 0; t < r->teams; ++t) {
+            uint64_t w = 0;
+            for (const dsr_dloop &L : r->loops) {
+                const uint64_t lo = std::min(L.dyn_start, (uint64_t)t * L.chunk);
+                const uint64_t hi = std::min(L.dyn_start, lo + L.chunk);
+                w += hi - lo;
+            }
+            items.push_back(item{w, (uint32_t)i, (uint32_t)t});
+        }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const item &a, const item &b) { return a.work > b.work; });
+    const size_t o_items = sz;
+    sz = align256(sz + items.size() * 2 * sizeof(uint32_t));
+    const size_t o_counter = sz;
+    sz = align256(sz + 2 * sizeof(uint32_t));
+    const size_t o_done = sz;
+    sz = align256(sz + ((size_t)n + 1) * sizeof(uint64_t));
+    (void)off_ops;
+
+    dsr_batch *b = new (std::nothrow) dsr_batch();
+    if (!b) return DSR_E_NOMEM;
+    b->ctx = ctx;
+    b->n = n;
+    b->graph = nullptr;
+    b->exec = nullptr;
+    b->own_stream = nullptr;
+    b->ev0 = b->ev1 = nullptr;
+    b->last = 0;
+    b->have_results = false;
+    b->variant = 0;
+    std::vector<uint8_t> stage;
+    try {
+        stage.assign(sz, 0);
+        b->teams.resize(n);
+        b->n_red.resize(n);
+        b->loops.resize(n);
+        b->h_results.resize(n);
+    } catch (...) {
+        delete b;
+        return DSR_E_NOMEM;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) { delete b; return DSR_E_HIP; }
+    if (hipMalloc((void **)&b->d_arena, sz) != hipSuccess) { delete b; return DSR_E_NOMEM; }
+    uint8_t *A = b->d_arena;
+    for (int32_t i = 0; i < n; ++i) {
+        const dsr_region *r = regions[i];
+        if (!r->ops.empty()) std::memcpy(stage.data() + o_ops[i], r->ops.data(), r->ops.size() * sizeof(dsr_op));
+        if (!r->loops.empty())
+            std::memcpy(stage.data() + o_loops[i], r->loops.data(), r->loops.size() * sizeof(dsr_dloop));
+        if (!r->init.empty()) std::memcpy(stage.data() + o_init[i], r->init.data(), r->init.size());
+        dsr_dregion R{};
+        R.ops = (const dsr_op *)(A + o_ops[i]);
+        R.loops = (const dsr_dloop *)(A + o_loops[i]);
+        R.init = A + o_init[i];
+        R.partials = (uint64_t *)(A + o_part[i]);
+        R.result = (dsr_dresult *)(A + o_res) + i;
+        R.trace = nullptr;
+        R.n_ops = (uint32_t)r->ops.size();
+        R.teams = (uint32_t)r->teams;
+        R.n_red = r->n_red;
+        R.red_kind_mask = r->red_kind_mask;
+        R.n_loops = (uint32_t)r->loops.size();
+        std::memcpy(stage.data() + o_reg + (size_t)i * sizeof(dsr_dregion), &R, sizeof(R));
+        b->teams[i] = r->teams;
+        b->n_red[i] = r->n_red;
+        b->loops[i] = r->loops;
+        b->variant = std::max(b->variant, r->variant);
+    }
+    uint32_t *it = (uint32_t *)(stage.data() + o_items);
+    for (size_t k = 0; k < items.size(); ++k) { it[2 * k] = items[k].r; it[2 * k + 1] = items[k].t; }
+    if (hipMemcpy(b->d_arena, stage.data(), sz, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(b->d_arena);
+        delete b;
+        return DSR_E_HIP;
+    }
+    b->d_regions = (dsr_dregion *)(A + o_reg);
+    b->d_results = (dsr_dresult *)(A + o_res);
+    b->d_items = (uint32_t *)(A + o_items);
+    b->n_items = (uint32_t)items.size();
+    b->d_counter = (uint32_t *)(A + o_counter);
+    b->d_done = (uint64_t *)(A + o_done);
+    int v = 0;
+    b->lds_max = kDefaultLdsPerWg;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) == hipSuccess && v > 0)
+        b->lds_max = (uint32_t)v;
+    b->cus = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && v > 0)
+        b->cus = (uint32_t)v;
+    if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
+        dsr_batch_free(b);
+        return DSR_E_HIP;
+    }
+    dsr_tune t{ctx->cfg.wg_size, ctx->cfg.lds_slab_bytes, ctx->cfg.overflow_threshold, ctx->cfg.master_joins, 0, 0};
+    const int rc = dsr_batch_tune(b, &t);
+    if (rc) {
+        dsr_batch_free(b);
+        return rc;
+    }
+    *out = b;
+    return DSR_OK;
+}
+
+static void drop_graph(dsr_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+extern "C" int dsr_batch_tune(dsr_batch *b, const dsr_tune *tune)
+{
+    if (!b || !tune) return DSR_E_INVAL;
+    dsr_tune t = *tune;
+    if (t.wg_size < 64 || t.wg_size > 1024 || (t.wg_size & 63u)) return DSR_E_INVAL;
+    if (t.lds_slab_bytes & 15u) return DSR_E_INVAL;
+    const uint32_t nw = t.wg_size / 64;
+    const uint64_t lds = (uint64_t)dsr::cb_bytes(nw) + t.lds_slab_bytes;
+    if (lds > b->lds_max) return DSR_E_LDS;
+    if (nw == 1) t.master_joins = 1;
+    /* the static share of a lane must stay within the exact bins' range */
+    const uint64_t lanes = 64ull * (t.master_joins ? nw : nw - 1);
+    for (int32_t i = 0; i < b->n; ++i)
+        for (const dsr_dloop &L : b->loops[i])
+            if ((L.chunk + lanes - 1) / lanes > (1ull << 15)) return DSR_E_INVAL;
+    const uint32_t variant = t.wg_size > 256 ? 0 : b->variant;
+    uint32_t grid = t.grid;
+    if (grid == 0) {
+        const int occ = dsr_region_kernel_occupancy(t.wg_size, (uint32_t)lds, variant);
+        if (occ <= 0) return DSR_E_LDS;
+        grid = (uint32_t)occ * (b->cus ? b->cus : 1);
+        grid = std::min(grid, b->ctx->cfg.max_teams);
+    }
+    grid = std::min(grid, b->n_items);
+    if (grid > b->ctx->cfg.max_teams) return DSR_E_NOMEM;
+    drop_graph(b);
+    t.grid = grid;
+    b->tune = t;
+    b->grid = grid;
+    b->lds_bytes = (uint32_t)lds;
+    return DSR_OK;
+}
+
+extern "C" int dsr_batch_get_tune(dsr_batch *b, dsr_tune *out)
+{
+    if (!b || !out) return DSR_E_INVAL;
+    *out = b->tune;
+    return DSR_OK;
+}
+
+static int batch_kernel(dsr_batch *b, hipStream_t s)
+{
+    dsr_dlaunch LP{};
+    LP.regions = b->d_regions;
+    LP.items = b->d_items;
+    LP.n_items = b->n_items;
+    LP.n_regions = (uint32_t)b->n;
+    LP.counter = b->d_counter;
+    LP.done_ts = b->d_done;
+    const dsr_dconfig C = make_dconfig(b->ctx, b->tune.wg_size, b->tune.lds_slab_bytes,
+                                       b->tune.overflow_threshold, b->tune.master_joins, 0);
+    return dsr_launch_region_kernel(&LP, &C, b->grid, b->tune.wg_size, b->lds_bytes, b->variant, s) ? DSR_E_HIP
+                                                                                                     : DSR_OK;
+}
+
+extern "C" int dsr_batch_launch(dsr_batch *b, void *stream)
+{
+    if (!b) return DSR_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (b->tune.use_graph) {
+        if (!s) {
+            if (!b->own_stream && hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking) != hipSuccess)
+                return DSR_E_HIP;
+            s = b->own_stream;
+        }
+        if (!b->exec) {
+            if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) return DSR_E_HIP;
+            const int rc = batch_kernel(b, s);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(s, &g);
+            if (rc || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return DSR_E_HIP;
+            }
+            b->graph = g;
+            if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+                drop_graph(b);
+                return DSR_E_HIP;
+            }
+        }
+        if (hipEventRecord(b->ev0, s) != hipSuccess) return DSR_E_HIP;
+        if (hipGraphLaunch(b->exec, s) != hipSuccess) return DSR_E_HIP;
+        if (hipEventRecord(b->ev1, s) != hipSuccess) return DSR_E_HIP;
+    } else {
+        if (hipEventRecord(b->ev0, s) != hipSuccess) return DSR_E_HIP;
+        const int rc = batch_kernel(b, s);
+        if (rc) return rc;
+        if (hipEventRecord(b->ev1, s) != hipSuccess) return DSR_E_HIP;
+    }
+    b->last = 1;
+    b->have_results = false;
+    return DSR_OK;
+}
+
+extern "C" int dsr_batch_launch_each(dsr_batch *b, void *stream)
+{
+    if (!b) return DSR_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const dsr_dconfig C = make_dconfig(b->ctx, b->tune.wg_size, b->tune.lds_slab_bytes,
+                                       b->tune.overflow_threshold, b->tune.master_joins, 0);
+    const uint32_t variant = b->tune.wg_size > 256 ? 0 : b->variant;
+    if (hipEventRecord(b->ev0, s) != hipSuccess) return DSR_E_HIP;
+    for (int32_t i = 0; i < b->n; ++i) {
+        dsr_dlaunch LP{};
+        LP.regions = b->d_regions + i;
+        LP.items = nullptr;
+        LP.n_regions = 1;
+        if (dsr_launch_region_kernel(&LP, &C, (uint32_t)b->teams[i], b->tune.wg_size, b->lds_bytes, variant, s))
+            return DSR_E_HIP;
+    }
+    if (hipEventRecord(b->ev1, s) != hipSuccess) return DSR_E_HIP;
+    b->last = 2;
+    b->have_results = false;
+    return DSR_OK;
+}
+
+extern "C" int dsr_batch_sync(dsr_batch *b)
+{
+    if (!b) return DSR_E_INVAL;
+    if (!b->last) return DSR_E_STATE;
+    if (hipEventSynchronize(b->ev1) != hipSuccess) return DSR_E_HIP;
+    if (hipMemcpy(b->h_results.data(), b->d_results, (size_t)b->n * sizeof(dsr_dresult),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return DSR_E_HIP;
+    b->have_results = true;
+    for (int32_t i = 0; i < b->n; ++i)
+        if (b->h_results[i].final_error) return b->h_results[i].final_error;
+    return DSR_OK;
+}
+
+extern "C" int dsr_batch_result(dsr_batch *b, int32_t r, int32_t index, int64_t *i64, double *f64,
+                                uint64_t *fixed3, int32_t *status)
+{
+    if (!b) return DSR_E_INVAL;
+    if (!b->have_results) return DSR_E_STATE;
+    if (r < 0 || r >= b->n || index < 0 || (uint32_t)index >= b->n_red[r]) return DSR_E_INVAL;
+    const dsr_dresult &R = b->h_results[r];
+    if (i64) *i64 = R.i64[index];
+    if (f64) *f64 = R.f64[index];
+    if (fixed3) for (int k = 0; k < 3; ++k) fixed3[k] = R.fixed[index][k];
+    if (status) *status = R.final_error;
+    return DSR_OK;
+}
+
+extern "C" int dsr_batch_times(dsr_batch *b, double *us, int32_t n)
+{
+    if (!b || !us || n < b->n) return DSR_E_INVAL;
+    if (b->last != 1) return DSR_E_STATE;
+    if (hipEventSynchronize(b->ev1) != hipSuccess) return DSR_E_HIP;
+    std::vector<uint64_t> t((size_t)b->n + 1);
+    if (hipMemcpy(t.data(), b->d_done, t.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return DSR_E_HIP;
+    for (int32_t i = 0; i < b->n; ++i) us[i] = ((double)t[i] - (double)t[b->n]) / 100.0;
+    return DSR_OK;
+}
+
+extern "C" int dsr_batch_elapsed(dsr_batch *b, float *ms)
+{
+    if (!b || !ms) return DSR_E_INVAL;
+    if (!b->last) return DSR_E_STATE;
+    if (hipEventSynchronize(b->ev1) != hipSuccess) return DSR_E_HIP;
+    return hipEventElapsedTime(ms, b->ev0, b->ev1) == hipSuccess ? DSR_OK : DSR_E_HIP;
+}
+
+extern "C" int dsr_batch_free(dsr_batch *b)
+{
+    if (!b) return DSR_E_INVAL;
+    if (b->last && b->ev1) (void)hipEventSynchronize(b->ev1);
+    drop_graph(b);
+    if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->d_arena) (void)hipFree(b->d_arena);
+    delete b;
+    return DSR_OK;
+}
+
+extern "C" int dsr_autotune(dsr_batch *b, const dsr_tune *cand, int32_t n_cand, int32_t reps, void *stream,
+                            dsr_tune *best, float *ms)
+{
+    if (!b || !cand || n_cand < 1 || reps < 1) return DSR_E_INVAL;
+    const dsr_tune keep = b->tune;
+    int32_t best_i = -1;
+    float best_ms = 0;
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t i = 0; i < n_cand; ++i) {
+        if (ms) ms[i] = -1.0f;
+        if (dsr_batch_tune(b, &cand[i]) != DSR_OK) continue;
+        int rc = dsr_batch_launch(b, s);                /* warm-up (and graph capture) */
+        if (rc == DSR_OK) rc = dsr_batch_sync(b);
+        if (rc != DSR_OK) continue;
+        float tot = 0;
+        bool ok = true;
+        for (int32_t k = 0; k < reps && ok; ++k) {
+            float t = 0;
+            ok = dsr_batch_launch(b, s) == DSR_OK && dsr_batch_elapsed(b, &t) == DSR_OK;
+            tot += t;
+        }
+        if (!ok) continue;
+        const float m = tot / reps;
+        if (ms) ms[i] = m;
+        if (best_i < 0 || m < best_ms) { best_i = i; best_ms = m; }
+    }
+    if (best_i < 0) {
+        (void)dsr_batch_tune(b, &keep);
+        return DSR_E_INVAL;
+    }
+    const int rc = dsr_batch_tune(b, &cand[best_i]);
+    if (best) *best = b->tune;
+    return rc;
+}
+
+/* ---- served form ------------------------------------------------------------ */
+namespace {
+
+struct serve_slot {
+    dsr_op *ops;            /* host-coherent */
+    dsr_dloop *loops;       /* host-coherent */
+    uint8_t *init;          /* host-coherent */
+    uint64_t *d_partials;   /* device */
+    dsr_dresult *d_result;  /* device */
+    bool busy;
+    uint64_t ticket;
+    uint32_t first_item;
+    uint64_t lds_cost, hbm_cost;
+};
+
+/* Peak LDS and HBM stack bytes one team of `r` needs under the device's
+ * placement rule; false if some frame fits neither space. */
+bool stack_peaks(const dsr_region *r, uint32_t lds_cap, uint32_t threshold, uint64_t hbm_cap,
+                 uint64_t *lds_peak, uint64_t *hbm_peak)
+{
+    uint64_t spl = 0, sph = 0;
+    *lds_peak = 0;
+    *hbm_peak = 0;
+    std::vector<std::pair<int, uint64_t>> live;
+    for (const dsr_op &op : r->ops) {
+        if (op.kind == DSR_OP_PUSH) {
+            const uint64_t size = ((uint64_t)op.nbytes + 15) & ~15ull;
+            if (size <= threshold && spl + size <= lds_cap) {
+                spl += size;
+                live.push_back({0, size});
+            } else if (sph + size <= hbm_cap) {
+                sph += size;
+                live.push_back({1, size});
+            } else {
+                return false;
+            }
+            *lds_peak = std::max(*lds_peak, spl);
+            *hbm_peak = std::max(*hbm_peak, sph);
+        } else if (op.kind == DSR_OP_POP && !live.empty()) {
+            if (live.back().first == 0) spl -= live.back().second; else sph -= live.back().second;
+            live.pop_back();
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
+struct dsr_server {
+    dsr_ctx *ctx;
+    dsr_serve_cfg cfg;
+    uint8_t *h_block;                 /* host-coherent control block         */
+    uint32_t *published;
+    uint32_t *stop;
+    uint32_t *exited;
+    uint64_t *start_ticks;
+    uint32_t *items;
+    dsr_dregion *regs;
+    dsr_drec *recs;
+    uint8_t *h_arena;                 /* host-coherent slot arenas            */
+    uint8_t *d_arena;                 /* device: partials, results, counter  */
+    uint32_t *d_counter;
+    std::vector<serve_slot> slots;
+    std::vector<uint32_t> free_slots;
+    uint32_t pub;
+    uint64_t next_ticket;
+    uint64_t lds_budget, hbm_budget, lds_used, hbm_used;
+    uint32_t grid, variant, lds_bytes;
+    dsr_tune tune;
+    hipStream_t stream;
+    uint32_t in_flight;
+};
+
+extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_server **out)
+{
+    if (!ctx || !cfg || !out) return DSR_E_INVAL;
+    *out = nullptr;
+    if (ctx->device < 0) return DSR_E_STATE;
+    dsr_serve_cfg c = *cfg;
+    if (c.slots == 0 || c.slots > 65536 || c.max_teams == 0 || c.slot_bytes == 0) return DSR_E_INVAL;
+    if (c.ring_items == 0) c.ring_items = 1u << 16;
+    if (c.ring_items & (c.ring_items - 1)) return DSR_E_INVAL;
+    if ((uint64_t)c.slots * c.max_teams > c.ring_items) return DSR_E_INVAL;
+    if (c.idle_ms == 0) c.idle_ms = 10000;
+    if (c.budget_pct == 0 || c.budget_pct > 100) c.budget_pct = 100;
+    dsr_tune t = c.tune;
+    if (t.wg_size < 64 || t.wg_size > 1024 || (t.wg_size & 63u) || (t.lds_slab_bytes & 15u)) return DSR_E_INVAL;
+    const uint32_t nw = t.wg_size / 64;
+    if (nw == 1) t.master_joins = 1;
+    int v = 0;
+    uint32_t lds_max = kDefaultLdsPerWg, cus = 1;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) == hipSuccess && v > 0)
+        lds_max = (uint32_t)v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && v > 0)
+        cus = (uint32_t)v;
+    const uint64_t lds = (uint64_t)dsr::cb_bytes(nw) + t.lds_slab_bytes + DSR_SERVE_LDS_BYTES;
+    if (lds > lds_max) return DSR_E_LDS;
+    const uint32_t variant = 0;
+    uint32_t grid = t.grid;
+    if (grid == 0) {
+        const int occ = dsr_region_kernel_occupancy(t.wg_size, (uint32_t)lds, variant);
+        if (occ <= 0) return DSR_E_LDS;
+        grid = std::min((uint32_t)occ * cus, ctx->cfg.max_teams);
+    }
+    if (grid > ctx->cfg.max_teams) return DSR_E_NOMEM;
+    t.grid = grid;
+
+    dsr_server *S = new (std::nothrow) dsr_server();
+    if (!S) return DSR_E_NOMEM;
+    S->ctx = ctx;
+    S->cfg = c;
+    S->tune = t;
+    S->grid = grid;
+    S->variant = variant;
+    S->lds_bytes = (uint32_t)lds;
+    S->pub = 0;
+    S->next_ticket = 1;
+    S->in_flight = 0;
+    S->lds_used = S->hbm_used = 0;
+    S->lds_budget = (uint64_t)grid * t.lds_slab_bytes * c.budget_pct / 100;
+    S->hbm_budget = (uint64_t)grid * ctx->cfg.hbm_slab_bytes * c.budget_pct / 100;
+    /* host-coherent control block: published, stop, start ticks, item ring,
+     * region descriptors, completion records */
+    const size_t o_items = 256, o_regs = o_items + align256((size_t)c.ring_items * 8);
+    const size_t o_recs = o_regs + align256((size_t)c.slots * sizeof(dsr_dregion));
+    const size_t blk = o_recs + align256((size_t)c.slots * sizeof(dsr_drec));
+    const size_t slot_h = align256(DSR_SERVE_MAX_OPS * sizeof(dsr_op)) +
+                          align256(DSR_SERVE_MAX_LOOPS * sizeof(dsr_dloop)) + align256(c.slot_bytes);
+    const size_t part_b = align256((size_t)DSR_MAX_RED * c.max_teams * 3 * sizeof(uint64_t));
+    const size_t slot_d = part_b + align256(sizeof(dsr_dresult));
+    if (hipSetDevice(ctx->device) != hipSuccess) { delete S; return DSR_E_HIP; }
+    if (hipHostMalloc((void **)&S->h_block, blk, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+        delete S;
+        return DSR_E_NOMEM;
+    }
+    std::memset(S->h_block, 0, blk);
+    if (hipHostMalloc((void **)&S->h_arena, slot_h * c.slots, hipHostMallocCoherent | hipHostMallocMapped) !=
+        hipSuccess) {
+        (void)hipHostFree(S->h_block);
+        delete S;
+        return DSR_E_NOMEM;
+    }
+    if (hipMalloc((void **)&S->d_arena, slot_d * c.slots + 256) != hipSuccess ||
+        hipMemset(S->d_arena, 0, slot_d * c.slots + 256) != hipSuccess) {
+        (void)hipHostFree(S->h_arena);
+        (void)hipHostFree(S->h_block);
+        delete S;
+        return DSR_E_NOMEM;
+    }
+    S->published = (uint32_t *)S->h_block;
+    S->stop = (uint32_t *)(S->h_block + 64);
+    S->start_ticks = (uint64_t *)(S->h_block + 128);
+    S->exited = (uint32_t *)(S->h_block + 192);
+    S->items = (uint32_t *)(S->h_block + o_items);
+    S->regs = (dsr_dregion *)(S->h_block + o_regs);
+    S->recs = (dsr_drec *)(S->h_block + o_recs);
+    S->d_counter = (uint32_t *)(S->d_arena + slot_d * c.slots);
+    S->slots.resize(c.slots);
+    for (uint32_t i = 0; i < c.slots; ++i) {
+        uint8_t *h = S->h_arena + slot_h * i;
+        serve_slot &sl = S->slots[i];
+        sl.ops = (dsr_op *)h;
+        sl.loops = (dsr_dloop *)(h + align256(DSR_SERVE_MAX_OPS * sizeof(dsr_op)));
+        sl.init = h + align256(DSR_SERVE_MAX_OPS * sizeof(dsr_op)) + align256(DSR_SERVE_MAX_LOOPS * sizeof(dsr_dloop));
+        sl.d_partials = (uint64_t *)(S->d_arena + slot_d * i);
+        sl.d_result = (dsr_dresult *)(S->d_arena + slot_d * i + part_b);
+        sl.busy = false;
+        S->free_slots.push_back(c.slots - 1 - i);
+    }
+    if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipFree(S->d_arena);
+        (void)hipHostFree(S->h_arena);
+        (void)hipHostFree(S->h_block);
+        delete S;
+        return DSR_E_HIP;
+    }
+    dsr_dlaunch LP{};
+    LP.regions = S->regs;
+    LP.items = S->items;
+    LP.n_items = 0;
+    LP.n_regions = c.slots;
+    LP.counter = S->d_counter;
+    LP.done_ts = S->start_ticks;
+    LP.published = S->published;
+    LP.stop = S->stop;
+    LP.recs = S->recs;
+    LP.ring_mask = c.ring_items - 1;
+    LP.idle_limit = (uint64_t)c.idle_ms * 100000ull;
+    LP.exited = S->exited;
+    dsr_dconfig C = make_dconfig(ctx, t.wg_size, t.lds_slab_bytes, t.overflow_threshold, t.master_joins, 0);
+    C.serve = 1;
+    if (dsr_launch_region_kernel(&LP, &C, grid, t.wg_size, S->lds_bytes, variant, S->stream) != 0) {
+        (void)hipStreamDestroy(S->stream);
+        (void)hipFree(S->d_arena);
+        (void)hipHostFree(S->h_arena);
+        (void)hipHostFree(S->h_block);
+        delete S;
+        return DSR_E_HIP;
+    }
+    *out = S;
+    return DSR_OK;
+}
+
+extern "C" int dsr_serve_submit(dsr_server *S, dsr_region *r, void *const *outs, int32_t n_outs,
+                                uint64_t *ticket)
+{
+    if (!S || !r || !ticket || n_outs < 0) return DSR_E_INVAL;
+    if (r->ctx != S->ctx) return DSR_E_INVAL;
+    /* a workgroup that left (idle timeout) means the server is going away */
+    if (__atomic_load_n(S->exited, __ATOMIC_ACQUIRE) != 0) return DSR_E_STATE;
+    if (!r->live.empty()) return DSR_E_LIVE;
+    if (r->ops.size() > DSR_SERVE_MAX_OPS || r->loops.size() > DSR_SERVE_MAX_LOOPS) return DSR_E_INVAL;
+    if ((uint32_t)r->teams > S->cfg.max_teams || r->init.size() > S->cfg.slot_bytes) return DSR_E_INVAL;
+    if ((size_t)n_outs > r->loops.size() || (n_outs && !outs)) return DSR_E_INVAL;
+    /* fixed-length chains beyond 8+8 run through the run-time loop here */
+    const uint64_t lanes = 64ull * (S->tune.master_joins ? S->tune.wg_size / 64 : S->tune.wg_size / 64 - 1);
+    for (const dsr_dloop &L : r->loops)
+        if ((L.chunk + lanes - 1) / lanes > (1ull << 15)) return DSR_E_INVAL;
+    uint64_t lp = 0, hp = 0;
+    const uint32_t thr = S->tune.overflow_threshold ? S->tune.overflow_threshold : 0xFFFFFFFFu;
+    if (!stack_peaks(r, S->tune.lds_slab_bytes, thr, S->ctx->cfg.hbm_slab_bytes, &lp, &hp)) return DSR_E_NOMEM;
+    const uint64_t lcost = lp * r->teams, hcost = hp * r->teams;
+    if (S->free_slots.empty()) return DSR_E_BUSY;
+    if (S->in_flight && (S->lds_used + lcost > S->lds_budget || S->hbm_used + hcost > S->hbm_budget))
+        return DSR_E_BUSY;
+    /* ring space: items of the oldest unfinished request bound the writer */
+    uint32_t floor_item = S->pub;
+    for (const serve_slot &sl : S->slots)
+        if (sl.busy && (int32_t)(sl.first_item - floor_item) < 0) floor_item = sl.first_item;
+    if (S->pub + (uint32_t)r->teams - floor_item > S->cfg.ring_items) return DSR_E_BUSY;
+
+    const uint32_t k = S->free_slots.back();
+    S->free_slots.pop_back();
+    serve_slot &sl = S->slots[k];
+    std::memcpy(sl.ops, r->ops.data(), r->ops.size() * sizeof(dsr_op));
+    std::vector<dsr_dloop> L = r->loops;
+    for (int32_t i = 0; i < n_outs; ++i)
+        if (outs[i]) L[i].out = outs[i];
+    if (!L.empty()) std::memcpy(sl.loops, L.data(), L.size() * sizeof(dsr_dloop));
+    if (!r->init.empty()) std::memcpy(sl.init, r->init.data(), r->init.size());
+    const uint64_t tk = S->next_ticket++;
+    dsr_dregion R{};
+    R.ops = sl.ops;
+    R.loops = sl.loops;
+    R.init = sl.init;
+    R.partials = sl.d_partials;
+    R.result = sl.d_result;
+    R.trace = nullptr;
+    R.n_ops = (uint32_t)r->ops.size();
+    R.teams = (uint32_t)r->teams;
+    R.n_red = r->n_red;
+    R.red_kind_mask = r->red_kind_mask;
+    R.tag = tk;
+    R.n_loops = (uint32_t)r->loops.size();
+    S->regs[k] = R;
+    for (int32_t t = 0; t < r->teams; ++t) {
+        const uint32_t it = (S->pub + (uint32_t)t) & (S->cfg.ring_items - 1);
+        S->items[2 * it] = k;
+        S->items[2 * it + 1] = (uint32_t)t;
+    }
+    sl.busy = true;
+    sl.ticket = tk;
+    sl.first_item = S->pub;
+    sl.lds_cost = lcost;
+    sl.hbm_cost = hcost;
+    S->lds_used += lcost;
+    S->hbm_used += hcost;
+    S->in_flight++;
+    S->pub += (uint32_t)r->teams;
+    /* everything above is visible before the new count */
+    __atomic_store_n(S->published, S->pub, __ATOMIC_RELEASE);
+    *ticket = tk;
+    return DSR_OK;
+}
+
+extern "C" int dsr_serve_poll(dsr_server *S, dsr_done *out, int32_t max)
+{
+    if (!S || (!out && max > 0)) return DSR_E_INVAL;
+    int32_t n = 0;
+    for (uint32_t k = 0; k < S->slots.size() && n < max; ++k) {
+        serve_slot &sl = S->slots[k];
+        if (!sl.busy) continue;
+        const uint64_t seq = __atomic_load_n(&S->recs[k].seq, __ATOMIC_ACQUIRE);
+        if (seq != sl.ticket) continue;
+        const dsr_drec &rec = S->recs[k];
+        dsr_done &d = out[n++];
+        std::memset(&d, 0, sizeof(d));
+        d.ticket = sl.ticket;
+        d.status = rec.status;
+        d.n_red = (int32_t)rec.n_red;
+        for (uint32_t i = 0; i < rec.n_red && i < 8; ++i) {
+            d.f64[i] = rec.f64[i];
+            d.i64[i] = rec.i64[i];
+            for (int w = 0; w < 3; ++w) d.fixed[i][w] = rec.fixed[i][w];
+        }
+        const uint64_t t0 = __atomic_load_n(S->start_ticks, __ATOMIC_ACQUIRE);
+        d.device_us = ((double)rec.ticks - (double)t0) / 100.0;
+        sl.busy = false;
+        S->lds_used -= sl.lds_cost;
+        S->hbm_used -= sl.hbm_cost;
+        S->in_flight--;
+        S->free_slots.push_back(k);
+    }
+    return n;
+}
+
+extern "C" int dsr_serve_pending(dsr_server *S)
+{
+    if (!S) return DSR_E_INVAL;
+    return (int)S->in_flight;
+}
+
+extern "C" int dsr_serve_stop(dsr_server *S)
+{
+    if (!S) return DSR_E_INVAL;
+    __atomic_store_n(S->stop, 1u, __ATOMIC_RELEASE);
+    const hipError_t e = hipStreamSynchronize(S->stream);
+    (void)hipStreamDestroy(S->stream);
+    (void)hipFree(S->d_arena);
+    (void)hipHostFree(S->h_arena);
+    (void)hipHostFree(S->h_block);
+    delete S;
+    return e == hipSuccess ? DSR_OK : DSR_E_HIP;
+}
+
+/* ---- schedule replays ------------------------------------------------------- */
+#include <chrono>
+
+namespace {
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+extern "C" int dsr_serve_replay(dsr_server *S, dsr_region *const *programs, const int32_t *prog,
+                                const double *arrival_s, int32_t n, void *const *slot_outs,
+                                int32_t n_loops_max, double timeout_s, double *latency_us, dsr_done *done)
+{
+    if (!S || !programs || !prog || !arrival_s || n < 0 || !latency_us || !done) return DSR_E_INVAL;
+    if (slot_outs && n_loops_max < 1) return DSR_E_INVAL;
+    std::vector<int32_t> by_ticket;       /* ticket - first ticket -> request */
+    const uint64_t first_ticket = S->next_ticket;
+    try {
+        by_ticket.assign((size_t)n, -1);
+    } catch (...) {
+        return DSR_E_NOMEM;
+    }
+    std::vector<dsr_done> buf(256);
+    const double t0 = now_s();
+    int32_t next = 0, completed = 0;
+    const double last = n ? arrival_s[n - 1] : 0.0;
+    while (completed < n) {
+        const double now = now_s() - t0;
+        while (next < n && arrival_s[next] <= now) {
+            dsr_region *r = programs[prog[next]];
+            if (S->free_slots.empty()) break;
+            const uint32_t slot = S->free_slots.back();
+            std::vector<void *> outs;
+            if (slot_outs)
+                for (size_t i = 0; i < r->loops.size(); ++i)
+                    outs.push_back(slot_outs[(size_t)slot * n_loops_max + i]);
+            uint64_t tk = 0;
+            const int rc = dsr_serve_submit(S, r, outs.empty() ? nullptr : outs.data(), (int32_t)outs.size(), &tk);
+            if (rc == DSR_E_BUSY) break;
+            if (rc) return rc;
+            by_ticket[tk - first_ticket] = next;
+            ++next;
+        }
+        const int got = dsr_serve_poll(S, buf.data(), (int32_t)buf.size());
+        if (got < 0) return got;
+        const double tdone = now_s() - t0;
+        for (int g = 0; g < got; ++g) {
+            const int32_t q = by_ticket[buf[g].ticket - first_ticket];
+            latency_us[q] = (tdone - arrival_s[q]) * 1e6;
+            done[q] = buf[g];
+            ++completed;
+        }
+        if (tdone > last + timeout_s) return DSR_E_BUSY;
+    }
+    return DSR_OK;
+}
+
+extern "C" int dsr_batch_replay_serial(dsr_batch *b, const int32_t *prog, const double *arrival_s, int32_t n,
+                                       double *latency_us)
+{
+    if (!b || !prog || !arrival_s || n < 0 || !latency_us) return DSR_E_INVAL;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return DSR_E_HIP;
+    const dsr_dconfig C = make_dconfig(b->ctx, b->tune.wg_size, b->tune.lds_slab_bytes,
+                                       b->tune.overflow_threshold, b->tune.master_joins, 0);
+    const uint32_t variant = b->tune.wg_size > 256 ? 0 : b->variant;
+    const double t0 = now_s();
+    int rc = DSR_OK;
+    for (int32_t q = 0; q < n && rc == DSR_OK; ++q) {
+        const int32_t i = prog[q];
+        if (i < 0 || i >= b->n) { rc = DSR_E_INVAL; break; }
+        while (now_s() - t0 < arrival_s[q]) {
+        }
+        dsr_dlaunch LP{};
+        LP.regions = b->d_regions + i;
+        LP.items = nullptr;
+        LP.n_regions = 1;
+        if (dsr_launch_region_kernel(&LP, &C, (uint32_t)b->teams[i], b->tune.wg_size, b->lds_bytes, variant, s) ||
+            hipStreamSynchronize(s) != hipSuccess)
+            rc = DSR_E_HIP;
+        latency_us[q] = (now_s() - t0 - arrival_s[q]) * 1e6;
+    }
+    (void)hipStreamDestroy(s);
+    b->last = 0;
+    if (rc == DSR_OK) {
+        if (hipMemcpy(b->h_results.data(), b->d_results, (size_t)b->n * sizeof(dsr_dresult),
+                      hipMemcpyDeviceToHost) != hipSuccess)
+            return DSR_E_HIP;
+        b->have_results = true;
+    }
+    return rc;
 }

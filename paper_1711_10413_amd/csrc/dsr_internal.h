@@ -10,6 +10,7 @@
 #define DSR_MAX_RED 8
 #define DSR_MAX_OPS 64
 #define DSR_MAX_LOOPS 16
+#define DSR_ARRIVE_GROUPS 32
 
 enum : uint32_t { DSR_OP_PUSH = 1, DSR_OP_PUBLISH = 2, DSR_OP_POP = 3 };
 
@@ -44,6 +45,9 @@ struct dsr_dresult {
     int32_t final_error;   /* the launch's error, written by the last team  */
     uint32_t done;         /* launch counter, bumped by the last team       */
     uint32_t claim[DSR_MAX_LOOPS]; /* dynamic-tail block counters; reset by the last team */
+    /* arrival tree: teams count into DSR_ARRIVE_GROUPS group counters (64 B
+     * apart), the last team of each group into `arrived` */
+    uint32_t group[DSR_ARRIVE_GROUPS * 16];
     uint64_t fixed[DSR_MAX_RED][3];
     double f64[DSR_MAX_RED];
     int64_t i64[DSR_MAX_RED];
@@ -61,6 +65,49 @@ struct dsr_dregion {
     uint32_t teams;
     uint32_t n_red;
     uint32_t red_kind_mask; /* bit r set: reduction r is FMA_CHAIN (exact fp64) */
+    uint64_t tag;           /* served form: request ticket written on completion */
+    uint32_t n_loops;
+    uint32_t pad;
+};
+
+/* Served form limits (a request's program is copied into LDS per item). */
+#define DSR_SERVE_MAX_OPS 16
+#define DSR_SERVE_MAX_LOOPS 4
+#define DSR_SERVE_LDS_BYTES (128 + DSR_SERVE_MAX_OPS * 48 + DSR_SERVE_MAX_LOOPS * 80)
+
+/* Served form: completion record of one request slot, in host-coherent
+ * memory.  The device fills it and then stores `seq` (the request ticket)
+ * with system-scope release; the host polls `seq`. */
+struct dsr_drec {
+    uint64_t seq;
+    int32_t status;
+    uint32_t n_red;
+    uint64_t ticks;         /* device wall clock at completion (100 MHz) */
+    double f64[DSR_MAX_RED];
+    int64_t i64[DSR_MAX_RED];
+    uint64_t fixed[DSR_MAX_RED][3];
+};
+
+/* What one launch runs.  Single region: regions[0] on gridDim.x teams,
+ * team = blockIdx.x.  Batch: persistent workgroups claim items (region,
+ * team) from counter[0] until n_items are done; the last workgroup to
+ * leave resets the counters. */
+struct dsr_dlaunch {
+    const dsr_dregion *regions;
+    const uint32_t *items;  /* [n_items][2] = {region, team}, or null */
+    uint32_t n_items;
+    uint32_t n_regions;
+    uint32_t *counter;      /* [0] next item, [1] workgroups finished */
+    uint64_t *done_ts;      /* per region: wall clock when its result was written;
+                               [n_regions]: when item 0 was claimed */
+    /* served form (published != null): items arrive over time in a ring */
+    const uint32_t *published; /* host-coherent: items published so far   */
+    const uint32_t *stop;      /* host-coherent: nonzero = drain and exit  */
+    dsr_drec *recs;            /* host-coherent completion records, per slot */
+    uint32_t ring_mask;        /* ring capacity - 1 (power of two)          */
+    uint32_t pad2;
+    uint32_t *exited;          /* host-coherent: workgroups that have left   */
+    uint64_t idle_limit;       /* exit after this many ticks with no new item */
 };
 
 /* Launch-wide configuration. */
@@ -72,16 +119,18 @@ struct dsr_dconfig {
     uint32_t threshold;
     uint32_t master_joins;
     uint32_t trace;
-    uint32_t pad;
+    uint32_t serve;        /* served form: per-item program copy after the stack */
 };
 
 #ifdef __cplusplus
 extern "C" {
 #endif
 /* Kernel launchers (dsr_kernels.hip). Return hipError_t as int. */
-int dsr_launch_region_kernel(const dsr_dregion *reg, const dsr_dconfig *cfg,
+int dsr_launch_region_kernel(const dsr_dlaunch *lp, const dsr_dconfig *cfg, uint32_t grid,
                              uint32_t wg_size, uint32_t lds_bytes, uint32_t variant,
                              void *stream);
+/* Workgroups of the region kernel that fit on one CU at once (0 on error). */
+int dsr_region_kernel_occupancy(uint32_t wg_size, uint32_t lds_bytes, uint32_t variant);
 #ifdef __cplusplus
 }
 #endif

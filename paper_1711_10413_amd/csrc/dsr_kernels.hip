@@ -502,6 +502,24 @@ __device__ __forceinline__ void body_gather_nested(team_t &T, AP arr, frame_t ou
     wave_sync();
 }
 
+/* Cross-team traffic (partials, arrival counters, results) uses
+ * device-scope relaxed atomics: on gfx950 these bypass the per-XCD L2,
+ * which is not coherent across XCDs, so no L2 write-back or invalidate
+ * (what a device-scope fence costs) is needed.  Ordering between a team's
+ * partial and its arrival is enforced by waiting for the partial's store
+ * to complete before the arrival atomic is issued. */
+__device__ __forceinline__ void store_dev(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t load_dev(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void drain_memory() { __builtin_amdgcn_s_waitcnt(0); }
+
 /* ---- region execution ---------------------------------------------------- */
 __device__ __forceinline__ const uint8_t *frame_ptr(const team_t &T, frame_t f)
 {
@@ -609,17 +627,22 @@ __device__ __forceinline__ span_t team_span(const dsr_dloop &L, uint32_t team, u
 
 /* Run one participating wave's share of a published body and join. */
 template <int VARIANT>
-__device__ __forceinline__ void participate(team_t &T, const dsr_dregion &R, const dsr_dconfig &C, uint32_t team,
-                            uint32_t body, frame_t f, uint32_t loop, uint32_t &inner_pushes)
+__device__ __forceinline__ void participate(team_t &T, const dsr_dregion &R, const dsr_dconfig &C,
+                                            uint32_t team, uint32_t body, frame_t f, uint32_t loop,
+                                            uint32_t &inner_pushes)
 {
     const uint32_t nwork = C.master_joins ? T.nw : T.nw - 1;
     const dsr_dloop &L = R.loops[loop];
     lane_acc A = acc_zero();
-    uint32_t *tr = C.trace ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
+    uint32_t *tr = (C.trace && R.trace) ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
     if (tr && T.lane == 0) tr[96 + 2 * T.wave] = (uint32_t)wall_clock64();
     run_body<VARIANT>(T, body, f, L, team_span(L, team, T.wave * 64 + T.lane, nwork * 64), A,
                       &R.result->claim[loop], T.wave, nwork, inner_pushes);
     if (tr && T.lane == 0) tr[97 + 2 * T.wave] = (uint32_t)wall_clock64();
+    /* served form: the request completes while the kernel keeps running,
+     * so this wave's output stores must have reached L2 before the join
+     * (the master then writes the L2 back before the team arrives) */
+    if (C.serve) drain_memory();
     const i192 w = wave_sum192(widen(A));
     const uint32_t bad = __any(A.bad != 0);
     end_parallel(T, w.w0, w.w1, w.w2, bad);
@@ -648,13 +671,15 @@ __device__ __forceinline__ void init_frame(team_t &T, frame_t f, const uint8_t *
     for (uint32_t o = nvec * 16 + T.lane; o < nbytes; o += 64) dst[o] = o < init_bytes ? src[o] : 0;
 }
 
-/* Master wave: the sequential code block (Figure 2). */
+/* Master wave: the sequential code block of one region for one team
+ * (Figure 2): pushes, publishes and pops.  Returns the team's error. */
 template <int VARIANT>
-__device__ __forceinline__ void master_program(team_t &T, const dsr_dregion &R, const dsr_dconfig &C, uint32_t team,
-                               uint32_t &barriers, uint32_t &inner_pushes)
+__device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, const dsr_dconfig &C,
+                                               uint32_t region, uint32_t team, uint32_t &barriers,
+                                               uint32_t &inner_pushes)
 {
     cb_header *h = header(T);
-    uint32_t *tr = C.trace ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
+    uint32_t *tr = (C.trace && R.trace) ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
     if (tr && T.lane == 0) tr[86] = (uint32_t)wall_clock64();
     wave_sync();
     int32_t err = 0;
@@ -680,6 +705,10 @@ __device__ __forceinline__ void master_program(team_t &T, const dsr_dregion &R, 
             f.space = uniform(ft[0]);
             f.off = uniform(ft[1]);
             f.size = uniform(ft[2]);
+            if (T.lane == 0) {
+                h->region = region;
+                h->team = team;
+            }
             publish(T, f, op.body, op.loop);
             barriers++;
             if (tr && T.lane == 0 && !stamped) {
@@ -730,7 +759,9 @@ __device__ __forceinline__ void master_program(team_t &T, const dsr_dregion &R, 
                 }
                 if (T.lane == 0) {
                     uint64_t *pp = R.partials + ((uint64_t)op.red * R.teams + team) * 3;
-                    pp[0] = slot.w0; pp[1] = slot.w1; pp[2] = slot.w2;
+                    store_dev(pp, slot.w0);
+                    store_dev(pp + 1, slot.w1);
+                    store_dev(pp + 2, slot.w2);
                 }
             }
             wave_sync();
@@ -747,15 +778,12 @@ __device__ __forceinline__ void master_program(team_t &T, const dsr_dregion &R, 
         }
     }
     (void)nwork;
-    /* terminate the workers (Figure 3's terminate branch) */
-    frame_t none{SPACE_NONE, 0, 0};
-    publish(T, none, DSR_BODY_TERMINATE, 0);
-    barriers++;
     if (tr && T.lane == 0) {
         tr[0] = npush;
         tr[81] = (uint32_t)err;
     }
     if (err && T.lane == 0) atomicCAS(&R.result->error, 0, err);
+    return err;
 }
 
 /* Last team: combine every team's partials, in 192-bit integers. */
@@ -765,8 +793,7 @@ __device__ __forceinline__ void combine_teams(const dsr_dregion &R, uint32_t lan
         i192 s{0, 0, 0};
         for (uint32_t t = lane; t < R.teams; t += 64) {
             const uint64_t *pp = R.partials + ((uint64_t)r * R.teams + t) * 3;
-            s = add192(s, i192{__builtin_nontemporal_load(pp), __builtin_nontemporal_load(pp + 1),
-                               __builtin_nontemporal_load(pp + 2)});
+            s = add192(s, i192{load_dev(pp), load_dev(pp + 1), load_dev(pp + 2)});
         }
         s = wave_sum192(s);
         if (lane == 0) {
@@ -779,35 +806,184 @@ __device__ __forceinline__ void combine_teams(const dsr_dregion &R, uint32_t lan
     }
 }
 
-__device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t lane)
+/* Served form: copy a finished region's result into its host-coherent
+ * completion record, then release the ticket. */
+__device__ __forceinline__ void publish_record(const dsr_dregion &R, dsr_drec *rec, uint32_t lane)
 {
-    __threadfence();
-    uint32_t prev = 0;
-    if (lane == 0) prev = atomicAdd(&R.result->arrived, 1u);
-    prev = (uint32_t)__shfl((int)prev, 0, 64);
-    if (prev == R.teams - 1) {
-        __threadfence();
-        combine_teams(R, lane);
-        if (lane < DSR_MAX_LOOPS) R.result->claim[lane] = 0;
-        if (lane == 0) {
-            R.result->final_error = atomicExch(&R.result->error, 0);
-            R.result->done += 1;
-            __threadfence();
-            atomicExch(&R.result->arrived, 0u);
-        }
+    if (lane != 0) return;
+    drain_memory();                      /* the result block is written */
+    for (uint32_t r = 0; r < R.n_red && r < DSR_MAX_RED; ++r) {
+        rec->f64[r] = R.result->f64[r];
+        rec->i64[r] = R.result->i64[r];
+        rec->fixed[r][0] = R.result->fixed[r][0];
+        rec->fixed[r][1] = R.result->fixed[r][1];
+        rec->fixed[r][2] = R.result->fixed[r][2];
     }
+    rec->status = R.result->final_error;
+    rec->n_red = R.n_red;
+    rec->ticks = wall_clock64();
+    __hip_atomic_store(&rec->seq, R.tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-template <int MAXWG, int VARIANT>
-__global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dregion R, dsr_dconfig C)
+/* A team's arrival after its program: the last team of the region
+ * combines the partials.  Arrivals go through a two-level tree (groups of
+ * teams, then groups) so that no counter sees more than a few dozen
+ * simultaneous atomics. */
+__device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team, uint32_t lane,
+                                            uint64_t *done_ts, dsr_drec *rec = nullptr)
 {
-    const uint32_t team = blockIdx.x;
+    const uint32_t gsize = (R.teams + DSR_ARRIVE_GROUPS - 1) / DSR_ARRIVE_GROUPS;
+    const uint32_t ngroups = (R.teams + gsize - 1) / gsize;
+    const uint32_t g = team / gsize;
+    const uint32_t in_group = min(gsize, R.teams - g * gsize);
+    drain_memory();                      /* this team's partials are stored */
+    uint32_t prev = 0;
+    if (lane == 0)
+        prev = __hip_atomic_fetch_add(&R.result->group[g * 16], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    prev = uniform((uint32_t)__shfl((int)prev, 0, 64));
+    if (prev != in_group - 1) return;
+    if (lane == 0) __hip_atomic_store(&R.result->group[g * 16], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (ngroups > 1) {
+        if (lane == 0)
+            prev = __hip_atomic_fetch_add(&R.result->arrived, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        prev = uniform((uint32_t)__shfl((int)prev, 0, 64));
+        if (prev != ngroups - 1) return;
+        if (lane == 0) __hip_atomic_store(&R.result->arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    int32_t err = 0;
+    if (lane == 0) err = __hip_atomic_exchange(&R.result->error, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    combine_teams(R, lane);
+    if (lane < DSR_MAX_LOOPS)
+        __hip_atomic_store(&R.result->claim[lane], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) {
+        R.result->final_error = err;
+        R.result->done += 1;
+        if (done_ts) *done_ts = wall_clock64();
+    }
+    if (rec) publish_record(R, rec, lane);
+}
+
+/* Served form: lane 0 polls the host's published count (system-scope
+ * acquire) with short sleeps.  Returns true once item `it` is published;
+ * false when the host asked to stop or nothing arrived for idle_limit
+ * ticks, so every wave reaches an exit. */
+__device__ __forceinline__ bool wait_published(const dsr_dlaunch &LP, uint32_t it, uint32_t lane)
+{
+    uint32_t ok = 0;
+    if (lane == 0) {
+        const uint64_t t0 = wall_clock64();
+        for (;;) {
+            const uint32_t pub = __hip_atomic_load(LP.published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (it < pub) { ok = 1; break; }
+            if (__hip_atomic_load(LP.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+            if (wall_clock64() - t0 > LP.idle_limit) break;
+            __builtin_amdgcn_s_sleep(8);
+        }
+    }
+    return __shfl((int)ok, 0, 64) != 0;
+}
+
+/* Served form: the request slot's descriptor, program and loop
+ * descriptors live in host memory that the host rewrites between
+ * requests; the master copies them into LDS with system-scope loads (never
+ * through the scalar cache, which is not kept coherent with the host) and
+ * points the copy's ops/loops at the LDS copies. */
+__device__ __forceinline__ dsr_dregion *serve_area(const team_t &T)
+{
+    return (dsr_dregion *)(T.stack_lds + T.lds_cap);
+}
+
+__device__ __forceinline__ void copy_words_sys(uint32_t *dst, const uint32_t *src, uint32_t words,
+                                               uint32_t lane)
+{
+    for (uint32_t k = lane; k < words; k += 64)
+        dst[k] = __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ const dsr_dregion &stage_request(team_t &T, const dsr_dregion *src)
+{
+    dsr_dregion *Rl = serve_area(T);
+    uint8_t *ops_l = (uint8_t *)Rl + 128;
+    uint8_t *loops_l = ops_l + DSR_SERVE_MAX_OPS * 48;
+    copy_words_sys((uint32_t *)Rl, (const uint32_t *)src, sizeof(dsr_dregion) / 4, T.lane);
+    wave_sync();
+    const uint32_t n_ops = min(uniform(Rl->n_ops), (uint32_t)DSR_SERVE_MAX_OPS);
+    const uint32_t n_loops = min(uniform(Rl->n_loops), (uint32_t)DSR_SERVE_MAX_LOOPS);
+    const dsr_op *ops_h = Rl->ops;
+    const dsr_dloop *loops_h = Rl->loops;
+    wave_sync();
+    copy_words_sys((uint32_t *)ops_l, (const uint32_t *)ops_h, n_ops * sizeof(dsr_op) / 4, T.lane);
+    copy_words_sys((uint32_t *)loops_l, (const uint32_t *)loops_h, n_loops * sizeof(dsr_dloop) / 4, T.lane);
+    wave_sync();
+    if (T.lane == 0) {
+        Rl->ops = (const dsr_op *)ops_l;
+        Rl->loops = (const dsr_dloop *)loops_l;
+        Rl->n_ops = n_ops;
+    }
+    wave_sync();
+    return *Rl;
+}
+
+/* One kernel for both launch forms.  The master wave runs region programs
+ * (one per workgroup for a single region; claimed items for a batch) and
+ * then terminates the workers; worker waves sit in the await loop and take
+ * the region and team of each published body from the control block. */
+template <int MAXWG, int VARIANT>
+__global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_dconfig C)
+{
     team_t T = team_init(dsr_lds, C.nw, C.lds_cap, C.threshold,
-                         C.hbm_base + (uint64_t)team * C.hbm_slot_bytes, (uint32_t)C.hbm_slot_bytes);
+                         C.hbm_base + (uint64_t)blockIdx.x * C.hbm_slot_bytes, (uint32_t)C.hbm_slot_bytes);
+    const bool single = LP.items == nullptr;
     uint32_t barriers = 0, inner_pushes = 0;
+    if (LP.published && blockIdx.x == 0 && T.wave == C.nw - 1 && T.lane == 0 && LP.done_ts)
+        __hip_atomic_store(LP.done_ts, wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     if (T.wave == C.nw - 1) {
-        master_program<VARIANT>(T, R, C, team, barriers, inner_pushes);
-        finish_team(R, T.lane);
+        for (uint32_t round = 0;; ++round) {
+            uint32_t region, team;
+            if (single) {
+                if (round) break;
+                region = 0;
+                team = blockIdx.x;
+            } else {
+                uint32_t it = 0;
+                if (T.lane == 0) it = atomicAdd(&LP.counter[0], 1u);
+                it = uniform((uint32_t)__shfl((int)it, 0, 64));
+                if (LP.published) {
+                    /* served form: wait until the host has published item
+                     * `it`; leave on stop or after idle_limit ticks without it */
+                    if (!wait_published(LP, it, T.lane)) break;
+                    const uint32_t k = it & LP.ring_mask;
+                    region = uniform(__hip_atomic_load(&LP.items[2 * k], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_SYSTEM));
+                    team = uniform(__hip_atomic_load(&LP.items[2 * k + 1], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_SYSTEM));
+                } else {
+                    if (it >= LP.n_items) break;
+                    if (it == 0 && LP.done_ts && T.lane == 0) LP.done_ts[LP.n_regions] = wall_clock64();
+                    region = uniform(LP.items[2 * it]);
+                    team = uniform(LP.items[2 * it + 1]);
+                }
+                team_reset(T);
+            }
+            const dsr_dregion &R = C.serve ? stage_request(T, LP.regions + region) : LP.regions[region];
+            run_program<VARIANT>(T, R, C, region, team, barriers, inner_pushes);
+            if (C.serve) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); /* outputs out of L2 */
+            finish_team(R, team, T.lane, (LP.done_ts && !LP.published) ? LP.done_ts + region : nullptr,
+                        LP.recs ? LP.recs + region : nullptr);
+        }
+        if (LP.exited && T.lane == 0)
+            __hip_atomic_fetch_add(LP.exited, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        /* terminate the workers (Figure 3's terminate branch) */
+        frame_t none{SPACE_NONE, 0, 0};
+        publish(T, none, DSR_BODY_TERMINATE, 0);
+        barriers++;
+        if (!single && !LP.published && T.lane == 0) {
+            if (__hip_atomic_fetch_add(&LP.counter[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                gridDim.x - 1) {
+                __hip_atomic_store(&LP.counter[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&LP.counter[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
     } else {
         for (;;) {
             uint32_t body, loop;
@@ -815,20 +991,22 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dregion R, dsr_dc
             const bool go = await(T, &body, &f, &loop);
             barriers++;
             if (!go) break;
-            participate<VARIANT>(T, R, C, team, body, f, loop, inner_pushes);
+            const uint32_t region = uniform(header(T)->region), team = uniform(header(T)->team);
+            participate<VARIANT>(T, C.serve ? *serve_area(T) : LP.regions[region], C, team, body, f, loop,
+                                 inner_pushes);
             barriers++;
         }
     }
-    if (C.trace && T.lane == 0) {
-        uint32_t *tr = R.trace + (uint64_t)team * DSR_TRACE_WORDS;
+    if (single && C.trace && LP.regions[0].trace && T.lane == 0) {
+        uint32_t *tr = LP.regions[0].trace + (uint64_t)blockIdx.x * DSR_TRACE_WORDS;
         tr[49 + T.wave] = barriers;
         tr[65 + T.wave] = inner_pushes;
     }
 }
 
 template <int MAXWG, int VARIANT>
-static hipError_t launch_variant(const dsr_dregion *reg, const dsr_dconfig *cfg, uint32_t wg_size,
-                                 uint32_t lds_bytes, hipStream_t s)
+static hipError_t launch_variant(const dsr_dlaunch *lp, const dsr_dconfig *cfg, uint32_t grid,
+                                 uint32_t wg_size, uint32_t lds_bytes, hipStream_t s)
 {
     static bool attr = false;
     if (!attr) {
@@ -836,20 +1014,42 @@ static hipError_t launch_variant(const dsr_dregion *reg, const dsr_dconfig *cfg,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL((dsr_region_kernel<MAXWG, VARIANT>), dim3(reg->teams), dim3(wg_size), lds_bytes,
-                       s, *reg, *cfg);
+    hipLaunchKernelGGL((dsr_region_kernel<MAXWG, VARIANT>), dim3(grid), dim3(wg_size), lds_bytes, s,
+                       *lp, *cfg);
     return hipGetLastError();
 }
 
-extern "C" int dsr_launch_region_kernel(const dsr_dregion *reg, const dsr_dconfig *cfg,
+extern "C" int dsr_launch_region_kernel(const dsr_dlaunch *lp, const dsr_dconfig *cfg, uint32_t grid,
                                         uint32_t wg_size, uint32_t lds_bytes, uint32_t variant,
                                         void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    if (wg_size > 256) return (int)launch_variant<1024, -1>(reg, cfg, wg_size, lds_bytes, s);
+    if (wg_size > 256) return (int)launch_variant<1024, -1>(lp, cfg, grid, wg_size, lds_bytes, s);
     switch (variant) {
-    case 0: return (int)launch_variant<256, 0>(reg, cfg, wg_size, lds_bytes, s);
-    case 1: return (int)launch_variant<256, 1>(reg, cfg, wg_size, lds_bytes, s);
-    default: return (int)launch_variant<256, 2>(reg, cfg, wg_size, lds_bytes, s);
+    case 0: return (int)launch_variant<256, 0>(lp, cfg, grid, wg_size, lds_bytes, s);
+    case 1: return (int)launch_variant<256, 1>(lp, cfg, grid, wg_size, lds_bytes, s);
+    default: return (int)launch_variant<256, 2>(lp, cfg, grid, wg_size, lds_bytes, s);
+    }
+}
+
+template <int MAXWG, int VARIANT>
+static int occupancy_of(uint32_t wg_size, uint32_t lds_bytes)
+{
+    (void)hipFuncSetAttribute((const void *)dsr_region_kernel<MAXWG, VARIANT>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)dsr_region_kernel<MAXWG, VARIANT>,
+                                                     (int)wg_size, lds_bytes) != hipSuccess)
+        return 0;
+    return n;
+}
+
+extern "C" int dsr_region_kernel_occupancy(uint32_t wg_size, uint32_t lds_bytes, uint32_t variant)
+{
+    if (wg_size > 256) return occupancy_of<1024, -1>(wg_size, lds_bytes);
+    switch (variant) {
+    case 0: return occupancy_of<256, 0>(wg_size, lds_bytes);
+    case 1: return occupancy_of<256, 1>(wg_size, lds_bytes);
+    default: return occupancy_of<256, 2>(wg_size, lds_bytes);
     }
 }

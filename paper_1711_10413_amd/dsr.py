@@ -46,7 +46,12 @@ DSR_TRACE_WORDS = 128
 # the exported C entry points (include/dsr.h)
 EXPORTS = ("dsr_init", "dsr_destroy", "dsr_region_begin", "dsr_push", "dsr_publish",
            "dsr_pop", "dsr_launch", "dsr_region_sync", "dsr_region_reduction",
-           "dsr_region_trace", "dsr_region_elapsed", "dsr_region_free", "dsr_strerror")
+           "dsr_region_trace", "dsr_region_elapsed", "dsr_region_free", "dsr_strerror",
+           "dsr_batch_create", "dsr_batch_tune", "dsr_batch_get_tune", "dsr_batch_launch",
+           "dsr_batch_launch_each", "dsr_batch_sync", "dsr_batch_result", "dsr_batch_times",
+           "dsr_batch_elapsed", "dsr_batch_free", "dsr_autotune", "dsr_batch_replay_serial",
+           "dsr_serve_start", "dsr_serve_submit", "dsr_serve_poll", "dsr_serve_pending",
+           "dsr_serve_replay", "dsr_serve_stop")
 
 
 class dsr_config(C.Structure):
@@ -61,6 +66,35 @@ class dsr_loop(C.Structure):
                 ("out", C.c_void_p), ("ni", C.c_uint32), ("nf", C.c_uint32),
                 ("alen", C.c_uint32), ("arrays", C.c_uint32), ("len", C.c_uint32),
                 ("schedule", C.c_uint32), ("tail_pct", C.c_uint32), ("block", C.c_uint32)]
+
+
+class dsr_tune(C.Structure):
+    _fields_ = [("wg_size", C.c_uint32), ("lds_slab_bytes", C.c_uint32),
+                ("overflow_threshold", C.c_uint32), ("master_joins", C.c_uint32),
+                ("grid", C.c_uint32), ("use_graph", C.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class dsr_serve_cfg(C.Structure):
+    _fields_ = [("tune", dsr_tune), ("slots", C.c_uint32), ("slot_bytes", C.c_uint32),
+                ("max_teams", C.c_uint32), ("ring_items", C.c_uint32), ("idle_ms", C.c_uint32),
+                ("budget_pct", C.c_uint32)]
+
+
+class dsr_done(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("status", C.c_int32), ("n_red", C.c_int32),
+                ("f64", C.c_double * 8), ("i64", C.c_int64 * 8), ("fixed", (C.c_uint64 * 3) * 8),
+                ("device_us", C.c_double)]
+
+    def as_dict(self):
+        fx = []
+        for i in range(self.n_red):
+            w = self.fixed[i]
+            fx.append(_fixed([w[0], w[1], w[2]]))
+        return {"ticket": self.ticket, "status": self.status, "f64": list(self.f64[:self.n_red]),
+                "i64": list(self.i64[:self.n_red]), "fixed": fx, "device_us": self.device_us}
 
 
 class DsrError(RuntimeError):
@@ -102,6 +136,29 @@ def lib():
             "dsr_region_trace": [P, i32, C.POINTER(u32), u32],
             "dsr_region_elapsed": [P, C.POINTER(C.c_float)],
             "dsr_region_free": [P],
+            "dsr_batch_create": [P, C.POINTER(P), i32, C.POINTER(P)],
+            "dsr_batch_tune": [P, C.POINTER(dsr_tune)],
+            "dsr_batch_get_tune": [P, C.POINTER(dsr_tune)],
+            "dsr_batch_launch": [P, P],
+            "dsr_batch_launch_each": [P, P],
+            "dsr_batch_sync": [P],
+            "dsr_batch_result": [P, i32, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                 C.POINTER(C.c_uint64), C.POINTER(i32)],
+            "dsr_batch_times": [P, C.POINTER(C.c_double), i32],
+            "dsr_batch_elapsed": [P, C.POINTER(C.c_float)],
+            "dsr_batch_free": [P],
+            "dsr_autotune": [P, C.POINTER(dsr_tune), i32, i32, P, C.POINTER(dsr_tune),
+                             C.POINTER(C.c_float)],
+            "dsr_batch_replay_serial": [P, C.POINTER(i32), C.POINTER(C.c_double), i32,
+                                        C.POINTER(C.c_double)],
+            "dsr_serve_start": [P, C.POINTER(dsr_serve_cfg), C.POINTER(P)],
+            "dsr_serve_submit": [P, P, C.POINTER(P), i32, C.POINTER(C.c_uint64)],
+            "dsr_serve_poll": [P, C.POINTER(dsr_done), i32],
+            "dsr_serve_pending": [P],
+            "dsr_serve_replay": [P, C.POINTER(P), C.POINTER(i32), C.POINTER(C.c_double), i32,
+                                 C.POINTER(P), i32, C.c_double, C.POINTER(C.c_double),
+                                 C.POINTER(dsr_done)],
+            "dsr_serve_stop": [P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -215,6 +272,156 @@ def dsr_region_free(region):
     return _check(lib().dsr_region_free(region), "dsr_region_free")
 
 
+# ---- batched form -----------------------------------------------------------
+def _fixed(w):
+    v = w[0] | (w[1] << 64) | (w[2] << 128)
+    return v - (1 << 192) if v >> 191 else v
+
+
+def dsr_batch_create(ctx, regions):
+    arr = (C.c_void_p * len(regions))(*[r.value if isinstance(r, C.c_void_p) else r for r in regions])
+    b = C.c_void_p()
+    _check(lib().dsr_batch_create(ctx, arr, len(regions), C.byref(b)), "dsr_batch_create")
+    return b
+
+
+def dsr_batch_tune(batch, wg_size=256, lds_slab_bytes=65536, overflow_threshold=0,
+                   master_joins=0, grid=0, use_graph=0):
+    t = dsr_tune(wg_size, lds_slab_bytes, overflow_threshold, master_joins, grid, use_graph)
+    return _check(lib().dsr_batch_tune(batch, C.byref(t)), "dsr_batch_tune")
+
+
+def dsr_batch_get_tune(batch):
+    t = dsr_tune()
+    _check(lib().dsr_batch_get_tune(batch, C.byref(t)), "dsr_batch_get_tune")
+    return t.as_dict()
+
+
+def dsr_batch_launch(batch, stream=0):
+    return _check(lib().dsr_batch_launch(batch, stream or None), "dsr_batch_launch")
+
+
+def dsr_batch_launch_each(batch, stream=0):
+    return _check(lib().dsr_batch_launch_each(batch, stream or None), "dsr_batch_launch_each")
+
+
+def dsr_batch_sync(batch):
+    rc = lib().dsr_batch_sync(batch)
+    if rc in (DSR_E_INVAL, DSR_E_STATE, DSR_E_HIP):
+        raise DsrError(rc, "dsr_batch_sync")
+    return rc
+
+
+def dsr_batch_result(batch, r, index=0):
+    """(int64 sum, float sum, exact total in 2**-75 units, status) of region r."""
+    i = C.c_int64()
+    f = C.c_double()
+    w = (C.c_uint64 * 3)()
+    st = C.c_int32()
+    _check(lib().dsr_batch_result(batch, r, index, C.byref(i), C.byref(f), w, C.byref(st)),
+           "dsr_batch_result")
+    return i.value, f.value, _fixed(w), st.value
+
+
+def dsr_batch_times(batch, n):
+    us = (C.c_double * n)()
+    _check(lib().dsr_batch_times(batch, us, n), "dsr_batch_times")
+    return np.frombuffer(us, dtype=np.float64).copy()
+
+
+def dsr_batch_elapsed(batch):
+    ms = C.c_float()
+    _check(lib().dsr_batch_elapsed(batch, C.byref(ms)), "dsr_batch_elapsed")
+    return ms.value
+
+
+def dsr_batch_free(batch):
+    return _check(lib().dsr_batch_free(batch), "dsr_batch_free")
+
+
+def dsr_autotune(batch, candidates, reps=3, stream=0):
+    """candidates: list of dicts of dsr_tune fields.  Returns (best dict,
+    list of mean ms per candidate, negative when skipped)."""
+    n = len(candidates)
+    arr = (dsr_tune * n)(*[dsr_tune(**{k: c.get(k, 0) for k, _ in dsr_tune._fields_})
+                           for c in candidates])
+    best = dsr_tune()
+    ms = (C.c_float * n)()
+    _check(lib().dsr_autotune(batch, arr, n, reps, stream or None, C.byref(best), ms),
+           "dsr_autotune")
+    return best.as_dict(), list(ms)
+
+
+def dsr_batch_replay_serial(batch, prog, arrival_s):
+    """One launch + synchronisation per request; returns latencies (us)."""
+    n = len(prog)
+    p = np.ascontiguousarray(prog, np.int32)
+    a = np.ascontiguousarray(arrival_s, np.float64)
+    lat = np.zeros(n, np.float64)
+    _check(lib().dsr_batch_replay_serial(batch, p.ctypes.data_as(C.POINTER(C.c_int32)),
+                                         a.ctypes.data_as(C.POINTER(C.c_double)), n,
+                                         lat.ctypes.data_as(C.POINTER(C.c_double))),
+           "dsr_batch_replay_serial")
+    return lat
+
+
+# ---- served form ------------------------------------------------------------
+def dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=65536, overflow_threshold=0, master_joins=0,
+                    grid=0, slots=256, slot_bytes=40960, max_teams=64, ring_items=1 << 16,
+                    idle_ms=10000, budget_pct=0):
+    cfg = dsr_serve_cfg(dsr_tune(wg_size, lds_slab_bytes, overflow_threshold, master_joins, grid, 0),
+                        slots, slot_bytes, max_teams, ring_items, idle_ms, budget_pct)
+    srv = C.c_void_p()
+    _check(lib().dsr_serve_start(ctx, C.byref(cfg), C.byref(srv)), "dsr_serve_start")
+    return srv
+
+
+def dsr_serve_submit(server, region, outs=None):
+    """Returns the ticket, or raises DsrError (BUSY: retry after polling)."""
+    tk = C.c_uint64()
+    if outs:
+        arr = (C.c_void_p * len(outs))(*outs)
+        rc = lib().dsr_serve_submit(server, region, arr, len(outs), C.byref(tk))
+    else:
+        rc = lib().dsr_serve_submit(server, region, None, 0, C.byref(tk))
+    _check(rc, "dsr_serve_submit")
+    return tk.value
+
+
+def dsr_serve_poll(server, max_n=256):
+    buf = (dsr_done * max_n)()
+    n = lib().dsr_serve_poll(server, buf, max_n)
+    if n < 0:
+        raise DsrError(n, "dsr_serve_poll")
+    return [buf[i].as_dict() for i in range(n)]
+
+
+def dsr_serve_pending(server):
+    return lib().dsr_serve_pending(server)
+
+
+def dsr_serve_replay(server, programs, prog, arrival_s, slot_outs=None, n_loops_max=1,
+                     timeout_s=60.0):
+    """Replay an arrival schedule; returns (latency_us array, list of done dicts)."""
+    n = len(prog)
+    progs = (C.c_void_p * len(programs))(*[r.value if isinstance(r, C.c_void_p) else r
+                                           for r in programs])
+    p = np.ascontiguousarray(prog, np.int32)
+    a = np.ascontiguousarray(arrival_s, np.float64)
+    lat = np.zeros(n, np.float64)
+    done = (dsr_done * max(n, 1))()
+    outs = (C.c_void_p * len(slot_outs))(*slot_outs) if slot_outs else None
+    _check(lib().dsr_serve_replay(server, progs, p.ctypes.data_as(C.POINTER(C.c_int32)),
+                                  a.ctypes.data_as(C.POINTER(C.c_double)), n, outs, n_loops_max,
+                                  timeout_s, lat.ctypes.data_as(C.POINTER(C.c_double)), done),
+           "dsr_serve_replay")
+    return lat, [done[i].as_dict() for i in range(n)]
+
+
+def dsr_serve_stop(server):
+    return _check(lib().dsr_serve_stop(server), "dsr_serve_stop")
+
+
 # ---- frame images for the bodies' layouts (include/dsr.h) -----------------
 def affine_xor_frame(a, b, c, d):
     """[0,8) int64 sum = 0; int32 a, b, c, d."""
@@ -235,3 +442,15 @@ def fma_chain_frame(s_i32, s_f64, arr=None):
 
 def gather_frame(arrays):
     return b"".join(np.asarray(a, np.int32).tobytes() for a in arrays)
+
+
+def fma_chain_region(ctx, teams, s_i32, s_f64, arr, n, x_ptr, y_ptr, schedule=0):
+    """A region whose masters share s_i32, s_f64 (and arr) in one frame and
+    publish the fma-chain loop over x[0..n) -> y (convenience builder)."""
+    img, size = fma_chain_frame(s_i32, s_f64, arr)
+    r = dsr_region_begin(ctx, teams)
+    f = dsr_push(r, size, img)
+    dsr_publish(r, f, DSR_BODY_FMA_CHAIN, n, inp=x_ptr, out=y_ptr, ni=len(s_i32), nf=len(s_f64),
+                alen=0 if arr is None else len(arr), schedule=schedule)
+    dsr_pop(r, f)
+    return r

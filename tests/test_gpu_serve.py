@@ -1,0 +1,189 @@
+"""GPU parity of the served form: a resident server kernel that admits
+region requests as they arrive (continuous batching), against the CPU
+oracle; each result must be the same alone and in the mix."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import dsr_workloads as W
+from oracle import ref as R
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from paper_1711_10413_amd import dsr as D  # noqa: E402
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def instances(n, seed=4, lcap=1 << 16):
+    Ls, Fs = W.cfg4_descriptors(n, seed=seed)
+    Ls = np.minimum(Ls, lcap)
+    out = []
+    for r in range(n):
+        ins = W.cfg4_instance(r, int(Ls[r]), int(Fs[r]), seed=seed)
+        x = W.instance_x(r, int(Ls[r]), seed=seed)
+        yr = R.fma_chain(x, ins.s_i32, ins.s_f64, ins.arr)
+        out.append((ins, x, yr, R.exact_sum(yr), R.fixed75_sum(yr)))
+    return out
+
+
+def programs(ctx, insts, chunk, xs, ys):
+    regs = []
+    for k, (ins, x, yr, rs, fx) in enumerate(insts):
+        teams = max(1, -(-ins.L // chunk))
+        regs.append(D.fma_chain_region(ctx, teams, ins.s_i32, ins.s_f64, ins.arr, ins.L,
+                                       xs[k].data_ptr(), ys[k].data_ptr()))
+    return regs
+
+
+def submit_retry(srv, region, outs=None, sink=None, timeout=60.0):
+    """Submit, polling completions into `sink` while the server is busy."""
+    t0 = time.time()
+    while True:
+        try:
+            return D.dsr_serve_submit(srv, region, outs)
+        except D.DsrError as e:
+            if e.code != D.DSR_E_BUSY:
+                raise
+            if sink is not None:
+                sink += D.dsr_serve_poll(srv)
+            assert time.time() - t0 < timeout, "admission never freed up"
+
+
+def drain(srv, want, timeout=60.0):
+    got = []
+    t0 = time.time()
+    while len(got) < want:
+        got += D.dsr_serve_poll(srv)
+        assert time.time() - t0 < timeout, "server did not finish"
+    return got
+
+
+@pytest.fixture(scope="module")
+def setup():
+    ctx = D.dsr_init(wg_size=256, lds_slab_bytes=32768, hbm_slab_bytes=65536, max_teams=2048)
+    insts = instances(48)
+    xs = [torch.from_numpy(x).cuda() for _, x, _, _, _ in insts]
+    ys = [torch.zeros(ins.L, dtype=torch.float64, device="cuda") for ins, *_ in insts]
+    regs = programs(ctx, insts, 8192, xs, ys)
+    torch.cuda.current_stream().synchronize()
+    yield ctx, insts, xs, ys, regs
+    for r in regs:
+        D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+
+
+def test_serve_output_visible_at_completion(setup):
+    """Each request's output must be fully visible to the host as soon as
+    its completion is polled, while the server keeps running."""
+    ctx, insts, xs, ys, regs = setup
+    say("serve visibility")
+    srv = D.dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=32768, slots=16, slot_bytes=40960,
+                            max_teams=64, idle_ms=20000)
+    try:
+        for k in range(12):
+            ins, x, yr, rs, fx = insts[k]
+            out = torch.zeros_like(ys[k])
+            torch.cuda.current_stream().synchronize()
+            D.dsr_serve_submit(srv, regs[k], [out.data_ptr()])
+            d = drain(srv, 1)[0]
+            assert d["status"] == 0 and d["f64"] == [rs]
+            assert np.array_equal(out.cpu().numpy().view(np.uint64), yr.view(np.uint64)), k
+    finally:
+        D.dsr_serve_stop(srv)
+
+
+def test_serve_requests_match_oracle(setup):
+    ctx, insts, xs, ys, regs = setup
+    say("serve basic")
+    srv = D.dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=32768, slots=64, slot_bytes=40960,
+                            max_teams=64, idle_ms=20000)
+    try:
+        # every instance twice, the second copy into a separate output buffer:
+        # both copies run concurrently in the mix
+        extra = [torch.zeros_like(y) for y in ys]
+        # the server runs on its own stream: buffers must be ready at submit
+        # (a device-wide synchronize would wait for the resident server)
+        torch.cuda.current_stream().synchronize()
+        tickets = {}
+        done = []
+        for k, r in enumerate(regs):
+            tickets[submit_retry(srv, r, sink=done)] = (k, ys[k])
+            tickets[submit_retry(srv, r, [extra[k].data_ptr()], sink=done)] = (k, extra[k])
+        done += drain(srv, len(tickets) - len(done))
+        assert D.dsr_serve_pending(srv) == 0
+        # outputs are complete when the request is: check them while the
+        # server is still resident (no kernel end has flushed anything)
+        for d in done:
+            k, y = tickets[d["ticket"]]
+            ins, x, yr, rs, fx = insts[k]
+            assert d["status"] == 0 and d["f64"] == [rs] and d["fixed"] == [fx], k
+        for k, (ins, x, yr, rs, fx) in enumerate(insts):
+            assert np.array_equal(ys[k].cpu().numpy().view(np.uint64), yr.view(np.uint64)), k
+            assert torch.equal(ys[k], extra[k])
+    finally:
+        D.dsr_serve_stop(srv)
+
+
+def test_serve_admission(setup):
+    ctx, insts, xs, ys, regs = setup
+    say("serve admission")
+    srv = D.dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=32768, slots=4, slot_bytes=40960,
+                            max_teams=64, idle_ms=20000)
+    try:
+        # a frame larger than both the LDS stack and the HBM slot: rejected
+        big = D.dsr_region_begin(ctx, 1)
+        f = D.dsr_push(big, 200000)
+        D.dsr_pop(big, f)
+        with pytest.raises(D.DsrError) as e:
+            D.dsr_serve_submit(srv, big)
+        assert e.value.code == D.DSR_E_NOMEM
+        D.dsr_region_free(big)
+        # more requests than slots: the fifth is deferred until one completes
+        n_ok = 0
+        for k in range(4):
+            D.dsr_serve_submit(srv, regs[k])
+            n_ok += 1
+        with pytest.raises(D.DsrError) as e:
+            D.dsr_serve_submit(srv, regs[4])
+        assert e.value.code == D.DSR_E_BUSY
+        done = drain(srv, n_ok)
+        assert all(d["status"] == 0 for d in done)
+        D.dsr_serve_submit(srv, regs[4])
+        done = drain(srv, 1)
+        assert done[0]["f64"] == [insts[4][3]]
+    finally:
+        D.dsr_serve_stop(srv)
+
+
+def test_serve_replay_and_serial(setup):
+    ctx, insts, xs, ys, regs = setup
+    say("serve replay")
+    arrivals = W.poisson_schedule(5000.0, 0.1, seed=4)
+    prog = (np.arange(len(arrivals)) * 7919) % len(regs)
+    slots = 32
+    pool = [torch.zeros(1 << 16, dtype=torch.float64, device="cuda") for _ in range(slots)]
+    torch.cuda.current_stream().synchronize()
+    srv = D.dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=32768, slots=slots,
+                            slot_bytes=40960, max_teams=64, idle_ms=20000)
+    try:
+        lat, done = D.dsr_serve_replay(srv, regs, prog, arrivals, [p.data_ptr() for p in pool], 1,
+                                       timeout_s=30.0)
+    finally:
+        D.dsr_serve_stop(srv)
+    assert np.all(lat > 0)
+    for q, d in enumerate(done):
+        ins, x, yr, rs, fx = insts[prog[q]]
+        assert d["status"] == 0 and d["f64"] == [rs] and d["fixed"] == [fx], q
+    # the comparison form: one launch + sync per request, same schedule
+    b = D.dsr_batch_create(ctx, regs)
+    lat2 = D.dsr_batch_replay_serial(b, prog, arrivals)
+    assert np.all(lat2 > 0)
+    for k, (ins, x, yr, rs, fx) in enumerate(insts):
+        if k in set(prog.tolist()):
+            assert D.dsr_batch_result(b, k)[1] == rs
+    D.dsr_batch_free(b)
