@@ -1,18 +1,28 @@
 """Benchmark of the data-sharing runtime on one MI355X.
 
-Workload (one step): the scalar-sharing sweep -- for each K in
-{1, 2, 4, 8, 16, 32, 64}, one region of 512 teams x 256 threads (one master
-wave, three worker waves) in which the master shares K scalars (ceil(K/2)
-int32, floor(K/2) fp64) through its LDS team stack and the workers run
-y[i] = fma chain over x[i] for 2**24 fp32 elements with an exact fp64 sum
-reduction into the shared slot.  Inputs are seeded synthetic data resident
-in HBM before timing; four (x, y) buffer sets rotate so the 256 MB
-Infinity Cache cannot hold the working set.
+Headline workload (one step): the scalar-sharing sweep.  For each K in
+{1, 2, 4, 8, 16, 32, 64} one region of 512 teams x 256 threads (one master
+wave, three worker waves): the master shares K scalars (ceil(K/2) int32,
+floor(K/2) fp64) through its LDS team stack, the workers run
+y[i] = fma chain over x[i] for 2**24 fp32 elements and reduce exactly into
+the shared slot.  `value` is region instances per second over the timed
+steps.  Inputs are seeded synthetic data resident in HBM before timing;
+four (x, y) buffer sets rotate so the 256 MB Infinity Cache cannot hold the
+working set.
 
-Prints one JSON line: region instances/s, the dominant kernel's roofline
-(algorithmic 12 B/element over its event-timed launch duration, against
-8 TB/s HBM), the same sweep with every frame forced into the HBM slab
-(global stack only), and the CPU oracle timed on a bounded sample.
+The same JSON line also reports the other workloads of the method:
+  plain      4 teams x 256, four shared int32 scalars, 1024 iterations:
+             region latency (launch + sync) and back-to-back rate
+  arrays     1-4 shared int32 arrays x {16, 256, 4096, 16384} elements,
+             two nested parallel levels, 2**26 outputs, 2048 teams:
+             LDS team stack vs HBM-only (global) stack
+  batched    10,000 regions with log-uniform loop lengths and frames in one
+             persistent launch (autotuned, hipGraph replay) vs one launch
+             per region: instances/s and p50/p99 completion
+  served     Poisson arrivals at 1k, 10k, 50k requests/s: p50/p99 latency
+             and instances/s, resident server vs one launch + sync per
+             request
+and the CPU oracle timed on a bounded sample (one thread).
 """
 import argparse
 import json
@@ -31,7 +41,17 @@ WG = 256
 SETS = 4
 
 
-def build_regions(D, ctx, xs, ys, ks, W, schedule=0):
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pct(a, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+# ---- scalar sweep (headline) -------------------------------------------------
+def build_sweep(D, ctx, xs, ys, ks, W, schedule=0):
     regions = {}
     for K in ks:
         cf, _ = W.cfg2_inputs(K, n=N, with_x=False)
@@ -47,14 +67,14 @@ def build_regions(D, ctx, xs, ys, ks, W, schedule=0):
 
 
 def time_sweep(torch, D, regions, ks, steps, warmup, stream):
-    """Run warmup + timed steps; returns (seconds, per-launch ms list)."""
+    """Warmup + timed steps.  One HIP event between consecutive launches on
+    the launch stream: a kernel's duration is bounded by the gap between the
+    events around it."""
     cur = torch.cuda.current_stream()
     for w in range(warmup):
         for K in ks:
             D.dsr_launch(regions[(K, w % SETS)], stream)
     torch.cuda.synchronize()
-    # one HIP event between consecutive launches on the launch stream: the
-    # i-th kernel's duration is bounded by the gap between events i and i+1
     evs = [torch.cuda.Event(enable_timing=True)]
     order = []
     t0 = time.perf_counter()
@@ -72,9 +92,325 @@ def time_sweep(torch, D, regions, ks, steps, warmup, stream):
     return secs, per
 
 
+def run_sweep(torch, np, D, W, args, stream):
+    dev = torch.device("cuda:0")
+    ks = list(W.CFG2_KS)
+    _, x_np = W.cfg2_inputs(1, n=N)
+    x0 = torch.from_numpy(x_np).to(dev)
+    xs = [x0] + [x0.clone() for _ in range(SETS - 1)]
+    ys = [torch.empty(N, dtype=torch.float64, device=dev) for _ in range(SETS)]
+    sched = 1 if args.schedule == "dynamic" else 0
+    ctx = D.dsr_init(wg_size=WG, lds_slab_bytes=4096, hbm_slab_bytes=4096, max_teams=TEAMS,
+                     master_joins=args.master_joins, flags=D.DSR_F_TRACE)
+    regions = build_sweep(D, ctx, xs, ys, ks, W, sched)
+    secs, per = time_sweep(torch, D, regions, ks, args.steps, args.warmup, stream)
+    n_regions = args.steps * len(ks)
+    avg_ms = sum(ms for _, ms in per) / len(per)
+    by_k = {K: float(np.mean([ms for k, ms in per if k == K])) for K in ks}
+    loop_us = {}
+    for K in ks:
+        r = regions[(K, (args.steps - 1) % SETS)]
+        tr = [D.dsr_region_trace(r, t) for t in range(TEAMS)]
+        loop_us[K] = (max(t["t_end"] for t in tr) - min(t["t_start"] for t in tr)) / 100.0
+    verified = None
+    if not args.no_verify:
+        from oracle import ref as R
+        verified = True
+        last = (args.steps - 1) % SETS
+        for K in ks:
+            r = regions[(K, last)]
+            if D.dsr_region_sync(r) != 0:
+                verified = False
+                continue
+            cf, _ = W.cfg2_inputs(K, n=N, with_x=False)
+            yr = R.fma_chain(x_np, cf.s_i32, cf.s_f64)
+            verified &= bool(D.dsr_region_reduction(r, 0)[1] == R.exact_sum(yr))
+            if K == ks[-1]:
+                verified &= bool(np.array_equal(ys[last].cpu().numpy(), yr))
+    hbm_only = None
+    if not args.no_hbm_only:
+        ctx2 = D.dsr_init(wg_size=WG, lds_slab_bytes=0, hbm_slab_bytes=4096, max_teams=TEAMS,
+                          master_joins=args.master_joins)
+        regions2 = build_sweep(D, ctx2, xs, ys, ks, W, sched)
+        secs2, per2 = time_sweep(torch, D, regions2, ks, args.steps, args.warmup, stream)
+        hbm_only = {"regions_per_s": n_regions / secs2,
+                    "kernel_ms_avg": sum(ms for _, ms in per2) / len(per2)}
+        for r in regions2.values():
+            D.dsr_region_free(r)
+        D.dsr_destroy(ctx2)
+    for r in regions.values():
+        D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+    del xs, ys, x0
+    torch.cuda.empty_cache()
+    algo = BYTES_PER_ELEM * N
+    return {
+        "value": n_regions / secs, "secs": secs, "avg_ms": avg_ms, "algo_bytes": algo,
+        "per_k_kernel_ms": by_k,
+        "per_k_gbs": {K: algo / (ms * 1e-3) / 1e9 for K, ms in by_k.items()},
+        "loop_phase_us": loop_us,
+        "loop_phase_gbs": {K: algo / (us * 1e-6) / 1e9 for K, us in loop_us.items()},
+        "lds_bytes_per_team": 704 + 4096, "hbm_only_stack": hbm_only, "verified": verified,
+    }
+
+
+# ---- plain region -------------------------------------------------------------
+def run_plain(torch, np, D, W, stream):
+    from oracle import ref as R
+    c = W.cfg1_inputs()
+    ctx = D.dsr_init(wg_size=256, lds_slab_bytes=4096, hbm_slab_bytes=4096, max_teams=4)
+    out = torch.zeros(1024, dtype=torch.int32, device="cuda")
+    r = D.dsr_region_begin(ctx, 4)
+    f = D.dsr_push(r, 24, D.affine_xor_frame(c.a, c.b, c.c, c.d))
+    D.dsr_publish(r, f, D.DSR_BODY_AFFINE_XOR, 1024, out=out.data_ptr())
+    D.dsr_pop(r, f)
+    for _ in range(20):
+        D.dsr_launch(r, stream)
+        D.dsr_region_sync(r)
+    lat = []
+    for _ in range(200):
+        t = time.perf_counter()
+        D.dsr_launch(r, stream)
+        D.dsr_region_sync(r)
+        lat.append((time.perf_counter() - t) * 1e6)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(1000):
+        D.dsr_launch(r, stream)
+    torch.cuda.synchronize()
+    rate = 1000 / (time.perf_counter() - t)
+    ro, rs = R.affine_xor(c.a, c.b, c.c, c.d, 0, 1024)
+    ok = D.dsr_region_sync(r) == 0 and D.dsr_region_reduction(r, 0)[0] == rs and \
+        bool(np.array_equal(out.cpu().numpy(), ro))
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+    return {"latency_us_p50": pct(lat, 50), "latency_us_p99": pct(lat, 99),
+            "back_to_back_regions_per_s": rate, "verified": ok}
+
+
+# ---- arrays + nesting -------------------------------------------------------
+def run_arrays(torch, np, D, W, stream, reps=6):
+    from oracle import ref as R
+    n, teams = 1 << 26, 2048
+    lds_max = 163840 - 704
+    outs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(2)]
+    res = {}
+    for A in W.CFG3_AS:
+        for length in W.CFG3_LENS:
+            arrs = W.cfg3_arrays(A, length)
+            frame = 4 * A * length
+            row = {"frame_bytes": frame}
+            for mode in ("lds", "hbm_only"):
+                slab = 0 if (mode == "hbm_only" or frame > lds_max) else (frame + 15) // 16 * 16
+                ctx = D.dsr_init(wg_size=256, lds_slab_bytes=slab,
+                                 hbm_slab_bytes=(frame + 15) // 16 * 16, max_teams=teams,
+                                 master_joins=1)
+                regs = []
+                for o in outs:
+                    r = D.dsr_region_begin(ctx, teams)
+                    f = D.dsr_push(r, frame, D.gather_frame(arrs))
+                    D.dsr_publish(r, f, D.DSR_BODY_GATHER_NESTED, n, out=o.data_ptr(), arrays=A,
+                                  length=length)
+                    D.dsr_pop(r, f)
+                    regs.append(r)
+                for k in range(2):
+                    D.dsr_launch(regs[k % 2], stream)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for k in range(reps):
+                    D.dsr_launch(regs[k % 2], stream)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                row[mode] = {"ms": ms, "gbs": 4.0 * n / (ms * 1e-3) / 1e9,
+                             "frame_in": "lds" if slab else "hbm", "lds_bytes_per_team": 704 + slab}
+                if mode == "lds":
+                    ok = D.dsr_region_sync(regs[(reps - 1) % 2]) == 0
+                    idx = np.random.default_rng(A * 7 + length).integers(0, n, 256)
+                    got = outs[(reps - 1) % 2].cpu().numpy()[idx]
+                    want = np.array([int(R.gather(arrs, int(i), int(i) + 1)[0]) for i in idx])
+                    row["verified_sample"] = bool(ok and np.array_equal(got, want))
+                for r in regs:
+                    D.dsr_region_free(r)
+                D.dsr_destroy(ctx)
+            row["lds_speedup"] = row["hbm_only"]["ms"] / row["lds"]["ms"]
+            res["A%d_len%d" % (A, length)] = row
+            say("arrays", A, length, round(row["lds"]["gbs"]), round(row["hbm_only"]["gbs"]))
+    del outs
+    torch.cuda.empty_cache()
+    return res
+
+
+# ---- batched -------------------------------------------------------------------
+def instance_pool(W, n, seed, lcap=None):
+    import numpy as np
+    Ls, Fs = W.cfg4_descriptors(n, seed=seed)
+    if lcap:
+        Ls = np.minimum(Ls, lcap)
+    offs = np.zeros(n + 1, np.int64)
+    offs[1:] = np.cumsum((Ls + 63) // 64 * 64)
+    return Ls, Fs, offs
+
+
+def fill_x(torch, W, Ls, offs, seed, dev):
+    """Generate every instance's x on the host in pieces of ~256 MB and
+    upload them into one device buffer."""
+    x = torch.empty(int(offs[-1]), dtype=torch.float32, device=dev)
+    n, r = len(Ls), 0
+    while r < n:
+        r1, tot = r, 0
+        while r1 < n and tot < (1 << 26):
+            tot += int(offs[r1 + 1] - offs[r1])
+            r1 += 1
+        host = torch.empty(int(offs[r1] - offs[r]), dtype=torch.float32).pin_memory()
+        hn = host.numpy()
+        for q in range(r, r1):
+            a = int(offs[q] - offs[r])
+            hn[a:a + int(Ls[q])] = W.instance_x(q, int(Ls[q]), seed=seed)
+        x[int(offs[r]):int(offs[r1])].copy_(host)
+        r = r1
+    return x
+
+
+def build_programs(D, W, ctx, Ls, Fs, offs, seed, x_ptr, y_ptr, chunk):
+    regs, insts = [], []
+    for q in range(len(Ls)):
+        ins = W.cfg4_instance(q, int(Ls[q]), int(Fs[q]), seed=seed)
+        teams = max(1, -(-int(Ls[q]) // chunk))
+        regs.append(D.fma_chain_region(ctx, teams, ins.s_i32, ins.s_f64, ins.arr, int(Ls[q]),
+                                       x_ptr + 4 * int(offs[q]), y_ptr + 8 * int(offs[q])))
+        insts.append(ins)
+    return regs, insts
+
+
+def run_batched(torch, np, D, W, stream, n_inst=10000, seed=3, sample=64):
+    from oracle import ref as R
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    Ls, Fs, offs = instance_pool(W, n_inst, seed)
+    x = fill_x(torch, W, Ls, offs, seed, dev)
+    y = torch.empty(int(offs[-1]), dtype=torch.float64, device=dev)
+    say("batched inputs", round(time.perf_counter() - t0, 1), "s")
+    ctx = D.dsr_init(wg_size=256, lds_slab_bytes=65536, hbm_slab_bytes=65536, max_teams=4096)
+    chunk = 65536
+    regs, insts = build_programs(D, W, ctx, Ls, Fs, offs, seed, x.data_ptr(), y.data_ptr(), chunk)
+    b = D.dsr_batch_create(ctx, regs)
+    for r in regs:
+        D.dsr_region_free(r)
+    torch.cuda.synchronize()
+    total_elems = int(Ls.sum())
+    algo = 12.0 * total_elems
+    cands = []
+    for wg in (128, 256, 512, 1024):
+        for lds in (16384, 40960, 65536):
+            for thr in (0, 8192):
+                cands.append(dict(wg_size=wg, lds_slab_bytes=lds, overflow_threshold=thr,
+                                  master_joins=1 if wg >= 512 else 0, use_graph=1))
+    best, ms = D.dsr_autotune(b, cands, reps=2, stream=stream)
+    say("autotune best", best)
+
+    def measure(launch, reps):
+        secs, lats = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            launch(b, stream)
+            st = D.dsr_batch_sync(b)
+            secs.append(time.perf_counter() - t)
+            lats.append(D.dsr_batch_times(b, n_inst))
+            assert st == 0, st
+        mid = int(np.argsort(secs)[len(secs) // 2])
+        s = secs[mid]
+        lat = lats[mid]
+        return {"ms": s * 1e3, "instances_per_s": n_inst / s, "gbs": algo / s / 1e9,
+                "p50_completion_us": pct(lat, 50), "p99_completion_us": pct(lat, 99),
+                "device_ms": D.dsr_batch_elapsed(b)}
+
+    pers = measure(D.dsr_batch_launch, 5)
+    rng = np.random.default_rng(1)
+    pick = rng.choice(n_inst, sample, replace=False)
+    ok = True
+    for q in pick:
+        ins = insts[q]
+        lo, hi = int(offs[q]), int(offs[q]) + ins.L
+        yr = R.fma_chain(x[lo:hi].cpu().numpy(), ins.s_i32, ins.s_f64, ins.arr)
+        _, f64, fixed, stq = D.dsr_batch_result(b, int(q))
+        ok &= (stq == 0 and f64 == R.exact_sum(yr) and fixed == R.fixed75_sum(yr))
+        ok &= bool(np.array_equal(y[lo:hi].cpu().numpy(), yr))
+    each = measure(D.dsr_batch_launch_each, 2)
+    D.dsr_batch_tune(b, **{k: best[k] for k in ("wg_size", "lds_slab_bytes", "overflow_threshold",
+                                                 "master_joins", "grid")}, use_graph=0)
+    plain = measure(D.dsr_batch_launch, 3)
+    D.dsr_batch_free(b)
+    D.dsr_destroy(ctx)
+    del x, y
+    torch.cuda.empty_cache()
+    return {"instances": n_inst, "elements": total_elems, "algorithmic_bytes": algo,
+            "tuned": best, "autotune_candidates": len(cands),
+            "persistent_graph": pers, "persistent_no_graph": plain,
+            "one_launch_per_region": each,
+            "speedup_vs_one_launch": each["ms"] / pers["ms"],
+            "verified_sample": {"instances": sample, "ok": bool(ok)}}
+
+
+# ---- served ----------------------------------------------------------------------
+def run_served(torch, np, D, W, stream, rates, seconds, pool=1000, seed=4, slots=256):
+    from oracle import ref as R
+    dev = torch.device("cuda:0")
+    Ls, Fs, offs = instance_pool(W, pool, seed)
+    x = fill_x(torch, W, Ls, offs, seed, dev)
+    y = torch.empty(int(offs[-1]), dtype=torch.float64, device=dev)
+    ctx = D.dsr_init(wg_size=256, lds_slab_bytes=32768, hbm_slab_bytes=65536, max_teams=4096)
+    chunk = 65536
+    regs, insts = build_programs(D, W, ctx, Ls, Fs, offs, seed, x.data_ptr(), y.data_ptr(), chunk)
+    slot_y = [torch.empty(1 << 20, dtype=torch.float64, device=dev) for _ in range(slots)]
+    torch.cuda.synchronize()
+    want = {}
+    for q in range(0, pool, 10):           # oracle results for a tenth of the pool
+        ins = insts[q]
+        lo = int(offs[q])
+        want[q] = R.exact_sum(R.fma_chain(x[lo:lo + ins.L].cpu().numpy(), ins.s_i32, ins.s_f64, ins.arr))
+    b = D.dsr_batch_create(ctx, regs)
+    res = {"pool_instances": pool, "seconds_per_rate": seconds, "slots": slots,
+           "request_to_instance": "request q runs instance q mod pool of the seed-4 table"}
+    for rate in rates:
+        arr = W.poisson_schedule(rate, seconds, seed=seed)
+        prog = (np.arange(len(arr)) % pool).astype(np.int32)
+        srv = D.dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=32768, slots=slots, slot_bytes=40960,
+                                max_teams=64, idle_ms=30000)
+        try:
+            lat, done = D.dsr_serve_replay(srv, regs, prog, arr, [t.data_ptr() for t in slot_y], 1,
+                                           timeout_s=60.0)
+        finally:
+            D.dsr_serve_stop(srv)
+        ok = all(d["status"] == 0 for d in done)
+        ok &= all(done[q]["f64"] == [want[int(prog[q])]] for q in range(len(done))
+                  if int(prog[q]) in want)
+        span = max(float(arr[-1]), 1e-9) if len(arr) else 1e-9
+        fin = float((arr + lat * 1e-6).max()) if len(arr) else 0.0
+        served = {"requests": int(len(arr)), "p50_us": pct(lat, 50), "p99_us": pct(lat, 99),
+                  "instances_per_s": len(arr) / max(fin, span), "verified": bool(ok)}
+        lat2 = D.dsr_batch_replay_serial(b, prog, arr)
+        fin2 = float((arr + lat2 * 1e-6).max()) if len(arr) else 0.0
+        serial = {"p50_us": pct(lat2, 50), "p99_us": pct(lat2, 99),
+                  "instances_per_s": len(arr) / max(fin2, span)}
+        res["%dk_per_s" % (rate // 1000)] = {"served": served, "serial_launch_sync": serial}
+        say("served", rate, served, serial)
+    D.dsr_batch_free(b)
+    for r in regs:
+        D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+    del x, y, slot_y
+    torch.cuda.empty_cache()
+    return res
+
+
+# ---- CPU baseline ---------------------------------------------------------------
 def cpu_baseline(W, seconds_target=12.0):
-    """The oracle, single-threaded, on a bounded sample of the same sweep:
-    the first 2**21 elements of x for every K (1/8 of each region)."""
+    """The oracle, single-threaded, on a bounded sample of the sweep: the
+    first 2**21 elements of x for every K (1/8 of each region)."""
     from oracle import ref as R
     sample = 1 << 21
     _, x = W.cfg2_inputs(1, n=sample)
@@ -82,15 +418,13 @@ def cpu_baseline(W, seconds_target=12.0):
     while True:
         for K in W.CFG2_KS:
             cf, _ = W.cfg2_inputs(K, n=sample, with_x=False)
-            y = R.fma_chain(x, cf.s_i32, cf.s_f64)
-            R.exact_sum(y)
+            R.exact_sum(R.fma_chain(x, cf.s_i32, cf.s_f64))
         passes += 1
         el = time.perf_counter() - t0
         if el >= seconds_target or passes >= 50:
             break
     regions_done = passes * len(W.CFG2_KS) * sample / N
-    return {"value": regions_done / el, "unit": "region instances/s", "cores": 1,
-            "kind": "oracle",
+    return {"value": regions_done / el, "unit": "region instances/s", "cores": 1, "kind": "oracle",
             "sample": "%d pass(es) of the K sweep over the first 2^21 of 2^24 elements "
                       "(fma chain + exact sum, C, one thread), %.1f s, scaled to whole "
                       "regions" % (passes, el)}
@@ -101,18 +435,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--parts", default="sweep,plain,arrays,batched,served,cpu",
+                    help="comma list of: sweep plain arrays batched served cpu")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-hbm-only", action="store_true")
     ap.add_argument("--master-joins", type=int, default=0)
-    ap.add_argument("--schedule", choices=["static", "dynamic"], default="static",
-                    help="loop schedule: static team ranges, or static + dynamic tail")
+    ap.add_argument("--schedule", choices=["static", "dynamic"], default="static")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="length of each served arrival schedule (the full workload is 60)")
+    ap.add_argument("--serve-rates", default="1000,10000,50000")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(regions shard by team blocks with one scalar exchange; see the design notes)",
-              file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (a region would "
+              "split by team blocks with one exact partial exchanged per GPU)", file=sys.stderr)
         sys.exit(2)
+    parts = set(args.parts.split(","))
 
     import numpy as np
     import torch
@@ -120,99 +457,46 @@ def main():
     from paper_1711_10413_amd import dsr as D
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream().cuda_stream
-    ks = list(W.CFG2_KS)
-
-    _, x_np = W.cfg2_inputs(1, n=N)
-    x0 = torch.from_numpy(x_np).to(dev)
-    xs = [x0] + [x0.clone() for _ in range(SETS - 1)]
-    ys = [torch.empty(N, dtype=torch.float64, device=dev) for _ in range(SETS)]
-
-    ctx = D.dsr_init(wg_size=WG, lds_slab_bytes=4096, hbm_slab_bytes=4096, max_teams=TEAMS,
-                     master_joins=args.master_joins, flags=D.DSR_F_TRACE)
-    sched = 1 if args.schedule == "dynamic" else 0
-    regions = build_regions(D, ctx, xs, ys, ks, W, sched)
-    secs, per = time_sweep(torch, D, regions, ks, args.steps, args.warmup, stream)
-    n_regions = args.steps * len(ks)
-    kern_ms = [ms for _, ms in per]
-    avg_ms = sum(kern_ms) / len(kern_ms)
-    by_k = {K: float(np.mean([ms for k, ms in per if k == K])) for K in ks}
-    # loop phase of each K's last launch: first worker release to last join
-    # over all teams, from the teams' 100 MHz wall-clock stamps
-    loop_us = {}
-    for K in ks:
-        r = regions[(K, (args.steps - 1) % SETS)]
-        tr = [D.dsr_region_trace(r, t) for t in range(TEAMS)]
-        loop_us[K] = (max(t["t_end"] for t in tr) - min(t["t_start"] for t in tr)) / 100.0
-
-    verified = None
-    if not args.no_verify:
-        from oracle import ref as R
-        verified = True
-        for K in ks:
-            r = regions[(K, (args.steps - 1) % SETS)]
-            if D.dsr_region_sync(r) != 0:
-                verified = False
-                continue
-            cf, _ = W.cfg2_inputs(K, n=N, with_x=False)
-            yr = R.fma_chain(x_np, cf.s_i32, cf.s_f64)
-            got = D.dsr_region_reduction(r, 0)[1]
-            verified &= bool(got == R.exact_sum(yr))
-            # the last step's y buffer holds the last K of the sweep
-            if K == ks[-1]:
-                yg = ys[(args.steps - 1) % SETS].cpu().numpy()
-                verified &= bool(np.array_equal(yg, yr))
-
-    hbm_only = None
-    if not args.no_hbm_only:
-        ctx2 = D.dsr_init(wg_size=WG, lds_slab_bytes=0, hbm_slab_bytes=4096, max_teams=TEAMS,
-                          master_joins=args.master_joins)
-        regions2 = build_regions(D, ctx2, xs, ys, ks, W, sched)
-        secs2, per2 = time_sweep(torch, D, regions2, ks, args.steps, args.warmup, stream)
-        hbm_only = {"regions_per_s": n_regions / secs2,
-                    "kernel_ms_avg": sum(ms for _, ms in per2) / len(per2)}
-        for r in regions2.values():
-            D.dsr_region_free(r)
-        D.dsr_destroy(ctx2)
-
-    for r in regions.values():
-        D.dsr_region_free(r)
-    D.dsr_destroy(ctx)
-
-    algo_bytes = BYTES_PER_ELEM * N
-    achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
-    out = {
-        "metric": "region instances/sec (scalar-sharing sweep, LDS team stack)",
-        "value": n_regions / secs,
-        "unit": "region instances/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": secs * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic (seeded splitmix64 inputs, resident in HBM)",
-        "config": {"workload": "scalar sweep: 512 teams x 256 threads, K in {1,2,4,8,16,32,64} "
-                               "shared scalars, 2^24 fp32 x -> fp64 y, exact fp64 sum",
-                   "teams": TEAMS, "wg_size": WG, "elements": N, "regions_per_step": len(ks),
-                   "buffer_sets": SETS, "master_joins": args.master_joins,
-                   "schedule": args.schedule},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "dsr_region_kernel", "algorithmic_bytes_per_launch": algo_bytes,
-                     "avg_launch_ms": avg_ms},
-        "per_k_kernel_ms": by_k,
-        "per_k_gbs": {K: algo_bytes / (ms * 1e-3) / 1e9 for K, ms in by_k.items()},
-        "loop_phase_us": loop_us,
-        "loop_phase_gbs": {K: algo_bytes / (us * 1e-6) / 1e9 for K, us in loop_us.items()},
-        "lds_bytes_per_team": 704 + 4096,
-        "hbm_only_stack": hbm_only,
-        "verified": verified,
-    }
-    if not args.no_cpu:
+    out = {"metric": "region instances/sec (scalar-sharing sweep, LDS team stack)",
+           "value": None, "unit": "region instances/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded splitmix64 inputs, resident in HBM)",
+           "config": {"workload": "scalar sweep: 512 teams x 256 threads, K in {1,2,4,8,16,32,64} "
+                                  "shared scalars, 2^24 fp32 x -> fp64 y, exact fp64 sum",
+                      "teams": TEAMS, "wg_size": WG, "elements": N, "regions_per_step": 7,
+                      "buffer_sets": SETS, "master_joins": args.master_joins,
+                      "schedule": args.schedule}}
+    if "sweep" in parts:
+        say("sweep")
+        sw = run_sweep(torch, np, D, W, args, stream)
+        out["value"] = sw["value"]
+        out["ms_per_step"] = sw["secs"] * 1e3 / args.steps
+        achieved = sw["algo_bytes"] / (sw["avg_ms"] * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": "dsr_region_kernel",
+                           "algorithmic_bytes_per_launch": sw["algo_bytes"],
+                           "avg_launch_ms": sw["avg_ms"]}
+        for k in ("per_k_kernel_ms", "per_k_gbs", "loop_phase_us", "loop_phase_gbs",
+                  "lds_bytes_per_team", "hbm_only_stack", "verified"):
+            out[k] = sw[k]
+    if "plain" in parts:
+        say("plain")
+        out["plain_region"] = run_plain(torch, np, D, W, stream)
+    if "arrays" in parts:
+        say("arrays")
+        out["arrays_nested"] = run_arrays(torch, np, D, W, stream)
+    if "batched" in parts:
+        say("batched")
+        out["batched"] = run_batched(torch, np, D, W, stream)
+    if "served" in parts:
+        say("served")
+        rates = [int(v) for v in args.serve_rates.split(",") if v]
+        out["served"] = run_served(torch, np, D, W, stream, rates, args.serve_seconds)
+    if "cpu" in parts:
+        say("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(out), flush=True)
 

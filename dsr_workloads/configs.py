@@ -11,7 +11,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .gen import (draws, uniform_int, uniform_f32, uniform_f64,
-                  log_uniform_int)
+                  log_uniform_int, uniform_f32_draws)
 
 CFG2_KS = (1, 2, 4, 8, 16, 32, 64)
 CFG3_AS = (1, 2, 3, 4)
@@ -57,13 +57,13 @@ def cfg2_inputs(K, seed=1, n=1 << 24, with_x=True):
     ni, nf = (K + 1) // 2, K // 2
     s_i = uniform_int(draws(seed, 0, 0, ni), I32_LO, I32_HI).astype(np.int32)
     s_f = uniform_f64(draws(seed, 1, 0, nf)) if nf else np.zeros(0, np.float64)
-    x = uniform_f32(draws(seed, 2, 0, n)) if with_x else None
+    x = uniform_f32_draws(seed, 2, 0, n) if with_x else None
     return Cfg2(K, s_i, s_f, n), x
 
 
 def cfg2_x_chunk(seed, start, count):
     """A slice of the cfg2 loop input x (for bounded samples)."""
-    return uniform_f32(draws(seed, 2, start, count))
+    return uniform_f32_draws(seed, 2, start, count)
 
 
 @dataclass
@@ -131,7 +131,7 @@ def cfg4_instance(r, L, F, seed=3):
 def instance_x(r, L, seed=3, start=0, count=None):
     """fp32 loop input of instance r, uniform on [-1, 1)."""
     count = L - start if count is None else count
-    return uniform_f32(draws(seed, _inst_stream(r, 2), start, count))
+    return uniform_f32_draws(seed, _inst_stream(r, 2), start, count)
 
 
 def poisson_schedule(rate, duration_s, seed=4):

@@ -271,9 +271,10 @@ int dsr_batch_sync(dsr_batch *b);
 int dsr_batch_result(dsr_batch *b, int32_t r, int32_t index, int64_t *i64, double *f64,
                      uint64_t *fixed3, int32_t *status);
 
-/* Completion times of the last persistent launch in microseconds after its
- * first item was claimed (from the device's 100 MHz clock): us[r] for
- * region r.  For dsr_batch_launch_each these are not recorded (DSR_E_STATE). */
+/* Completion times of the last launch in microseconds on the device's
+ * 100 MHz clock: us[r] for region r, counted from the first item's claim
+ * (persistent form) or from the start of the first region's kernel (one
+ * launch per region). */
 int dsr_batch_times(dsr_batch *b, double *us, int32_t n);
 
 /* Duration of the last launch (either form) in milliseconds, from HIP
@@ -382,6 +383,57 @@ int dsr_batch_replay_serial(dsr_batch *b, const int32_t *prog, const double *arr
 /* Stop the server: the kernel drains the published items and exits; then
  * frees the server.  Completed requests not yet polled are dropped. */
 int dsr_serve_stop(dsr_server *s);
+
+/* ---- footprint and occupancy model ------------------------------------------
+ * How many teams a compute unit holds at once, and what limits it, from
+ * the resources one team needs (section 6.2: teams per SM from registers
+ * per thread, threads per team, shared memory per team and the hardware's
+ * block cap; section 8 notes such a model is easy to build).  Pure host
+ * arithmetic: with K40/P100 parameters it reproduces the paper's
+ * Tables 4-7, with gfx950's it predicts this runtime's occupancy. */
+typedef struct dsr_hw_model {
+    uint32_t compute_units;
+    uint32_t regs_per_cu;          /* 32-bit registers per CU (SM)            */
+    uint32_t reg_granule;          /* registers per thread are allocated in
+                                      multiples of this                       */
+    uint32_t max_teams_per_cu;     /* concurrent workgroups (blocks) per CU   */
+    uint32_t max_threads_per_cu;
+    uint32_t shared_per_cu;        /* shared memory (LDS) bytes per CU        */
+    uint32_t shared_granule;       /* shared memory allocation granule        */
+    uint32_t simds_per_cu;         /* 0: registers are one pool per CU (the
+                                      paper's SM model); else each SIMD owns
+                                      regs_per_cu / simds_per_cu registers
+                                      and holds whole waves                   */
+    uint32_t wave_size;            /* lanes per wave (used when simds_per_cu) */
+} dsr_hw_model;
+
+#define DSR_LIMIT_TEAMS      0     /* the hardware's workgroup cap            */
+#define DSR_LIMIT_REGISTERS  1
+#define DSR_LIMIT_SHARED     2
+#define DSR_LIMIT_THREADS    3
+
+typedef struct dsr_occupancy {
+    uint32_t teams_per_cu;
+    uint32_t teams_by_registers;
+    uint32_t teams_by_shared;
+    uint32_t teams_by_threads;
+    uint32_t limiter;              /* DSR_LIMIT_*                             */
+    uint32_t shared_per_team;      /* bytes, as allocated                     */
+    uint64_t shared_per_cu;        /* teams_per_cu * shared_per_team          */
+    uint32_t regs_per_thread;      /* as allocated                            */
+    uint32_t hip_teams_per_cu;     /* dsr_region_occupancy: the HIP runtime's
+                                      own answer for the kernel (0 otherwise) */
+} dsr_occupancy;
+
+int dsr_occupancy_model(const dsr_hw_model *hw, uint32_t threads_per_team,
+                        uint32_t regs_per_thread, uint32_t shared_per_team,
+                        dsr_occupancy *out);
+
+/* The model for this runtime's region kernel on the context's device: the
+ * kernel's registers per thread (compiled variant `variant`, 0..2, of the
+ * context's workgroup size), the team's LDS (control block plus stack
+ * slab) and the device's parameters. */
+int dsr_region_occupancy(dsr_ctx *ctx, uint32_t variant, dsr_occupancy *out);
 
 /* Static string for a DSR_* code. */
 const char *dsr_strerror(int code);

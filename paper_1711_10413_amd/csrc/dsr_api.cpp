@@ -761,6 +761,8 @@ extern "C" int dsr_batch_launch_each(dsr_batch *b, void *stream)
         LP.regions = b->d_regions + i;
         LP.items = nullptr;
         LP.n_regions = 1;
+        LP.done_ts = b->d_done + i;                  /* region i's completion */
+        LP.start_ts = i == 0 ? b->d_done + b->n : nullptr;
         if (dsr_launch_region_kernel(&LP, &C, (uint32_t)b->teams[i], b->tune.wg_size, b->lds_bytes, variant, s))
             return DSR_E_HIP;
     }
@@ -801,7 +803,7 @@ extern "C" int dsr_batch_result(dsr_batch *b, int32_t r, int32_t index, int64_t 
 extern "C" int dsr_batch_times(dsr_batch *b, double *us, int32_t n)
 {
     if (!b || !us || n < b->n) return DSR_E_INVAL;
-    if (b->last != 1) return DSR_E_STATE;
+    if (b->last != 1 && b->last != 2) return DSR_E_STATE;
     if (hipEventSynchronize(b->ev1) != hipSuccess) return DSR_E_HIP;
     std::vector<uint64_t> t((size_t)b->n + 1);
     if (hipMemcpy(t.data(), b->d_done, t.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
@@ -1284,4 +1286,63 @@ extern "C" int dsr_batch_replay_serial(dsr_batch *b, const int32_t *prog, const 
         b->have_results = true;
     }
     return rc;
+}
+
+/* ---- footprint and occupancy model ------------------------------------------ */
+extern "C" int dsr_occupancy_model(const dsr_hw_model *hw, uint32_t threads, uint32_t regs,
+                                   uint32_t shared, dsr_occupancy *out)
+{
+    if (!hw || !out || threads == 0 || regs == 0) return DSR_E_INVAL;
+    if (hw->regs_per_cu == 0 || hw->max_teams_per_cu == 0 || hw->max_threads_per_cu == 0) return DSR_E_INVAL;
+    const uint32_t rg = hw->reg_granule ? hw->reg_granule : 1;
+    const uint32_t sg = hw->shared_granule ? hw->shared_granule : 1;
+    const uint64_t r = ((uint64_t)regs + rg - 1) / rg * rg;
+    const uint64_t sh = ((uint64_t)shared + sg - 1) / sg * sg;
+    dsr_occupancy o{};
+    o.regs_per_thread = (uint32_t)r;
+    o.shared_per_team = (uint32_t)sh;
+    if (hw->simds_per_cu && hw->wave_size) {
+        /* registers live in the SIMDs' files: a SIMD holds as many waves as
+         * its file has room for, and a team needs ceil(threads / wave) of
+         * the CU's waves */
+        const uint64_t per_lane = hw->regs_per_cu / ((uint64_t)hw->simds_per_cu * hw->wave_size);
+        const uint64_t waves = per_lane / r * hw->simds_per_cu;
+        const uint64_t team_waves = (threads + hw->wave_size - 1) / hw->wave_size;
+        o.teams_by_registers = (uint32_t)(waves / team_waves);
+    } else {
+        o.teams_by_registers = (uint32_t)(hw->regs_per_cu / (r * threads));
+    }
+    o.teams_by_shared = sh ? (uint32_t)std::min<uint64_t>(hw->shared_per_cu / sh, 0xFFFFFFFFu) : 0xFFFFFFFFu;
+    o.teams_by_threads = hw->max_threads_per_cu / threads;
+    uint32_t t = hw->max_teams_per_cu;
+    uint32_t lim = DSR_LIMIT_TEAMS;
+    if (o.teams_by_registers < t) { t = o.teams_by_registers; lim = DSR_LIMIT_REGISTERS; }
+    if (o.teams_by_shared < t) { t = o.teams_by_shared; lim = DSR_LIMIT_SHARED; }
+    if (o.teams_by_threads < t) { t = o.teams_by_threads; lim = DSR_LIMIT_THREADS; }
+    o.teams_per_cu = t;
+    o.limiter = lim;
+    o.shared_per_cu = (uint64_t)t * sh;
+    *out = o;
+    return DSR_OK;
+}
+
+extern "C" int dsr_region_occupancy(dsr_ctx *ctx, uint32_t variant, dsr_occupancy *out)
+{
+    if (!ctx || !out || variant > 2) return DSR_E_INVAL;
+    if (ctx->device < 0) return DSR_E_STATE;
+    hipDeviceProp_t p{};
+    if (hipGetDeviceProperties(&p, ctx->device) != hipSuccess) return DSR_E_HIP;
+    const int regs = dsr_region_kernel_regs(ctx->cfg.wg_size, variant);
+    if (regs <= 0 || p.multiProcessorCount <= 0 || p.maxThreadsPerMultiProcessor <= 0 || p.warpSize <= 0)
+        return DSR_E_HIP;
+    /* gfx950: 4 SIMDs, each with 512 VGPRs (arch + acc) per lane, allocated
+     * in 8s; the workgroup cap is one per wave slot, so waves, registers
+     * and LDS are what limit a team */
+    const uint32_t wave = (uint32_t)p.warpSize, thr = (uint32_t)p.maxThreadsPerMultiProcessor;
+    dsr_hw_model hw{(uint32_t)p.multiProcessorCount, 4u * 512u * wave, 8u, thr / wave, thr,
+                    (uint32_t)p.maxSharedMemoryPerMultiProcessor, 128u, 4u, wave};
+    const int rc = dsr_occupancy_model(&hw, ctx->cfg.wg_size, (uint32_t)regs, ctx->lds_bytes, out);
+    if (rc) return rc;
+    out->hip_teams_per_cu = (uint32_t)dsr_region_kernel_occupancy(ctx->cfg.wg_size, ctx->lds_bytes, variant);
+    return DSR_OK;
 }

@@ -107,6 +107,7 @@ struct dsr_dlaunch {
     uint32_t ring_mask;        /* ring capacity - 1 (power of two)          */
     uint32_t pad2;
     uint32_t *exited;          /* host-coherent: workgroups that have left   */
+    uint64_t *start_ts;        /* if set, block 0 stamps its start time here */
     uint64_t idle_limit;       /* exit after this many ticks with no new item */
 };
 
@@ -131,6 +132,8 @@ int dsr_launch_region_kernel(const dsr_dlaunch *lp, const dsr_dconfig *cfg, uint
                              void *stream);
 /* Workgroups of the region kernel that fit on one CU at once (0 on error). */
 int dsr_region_kernel_occupancy(uint32_t wg_size, uint32_t lds_bytes, uint32_t variant);
+/* Registers per thread of the region kernel variant (0 on error). */
+int dsr_region_kernel_regs(uint32_t wg_size, uint32_t variant);
 #ifdef __cplusplus
 }
 #endif

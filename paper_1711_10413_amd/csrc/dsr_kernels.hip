@@ -937,6 +937,7 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
     uint32_t barriers = 0, inner_pushes = 0;
     if (LP.published && blockIdx.x == 0 && T.wave == C.nw - 1 && T.lane == 0 && LP.done_ts)
         __hip_atomic_store(LP.done_ts, wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (LP.start_ts && blockIdx.x == 0 && T.wave == C.nw - 1 && T.lane == 0) *LP.start_ts = wall_clock64();
     if (T.wave == C.nw - 1) {
         for (uint32_t round = 0;; ++round) {
             uint32_t region, team;
@@ -1051,5 +1052,23 @@ extern "C" int dsr_region_kernel_occupancy(uint32_t wg_size, uint32_t lds_bytes,
     case 0: return occupancy_of<256, 0>(wg_size, lds_bytes);
     case 1: return occupancy_of<256, 1>(wg_size, lds_bytes);
     default: return occupancy_of<256, 2>(wg_size, lds_bytes);
+    }
+}
+
+template <int MAXWG, int VARIANT>
+static int regs_of()
+{
+    hipFuncAttributes a{};
+    if (hipFuncGetAttributes(&a, (const void *)dsr_region_kernel<MAXWG, VARIANT>) != hipSuccess) return 0;
+    return a.numRegs;
+}
+
+extern "C" int dsr_region_kernel_regs(uint32_t wg_size, uint32_t variant)
+{
+    if (wg_size > 256) return regs_of<1024, -1>();
+    switch (variant) {
+    case 0: return regs_of<256, 0>();
+    case 1: return regs_of<256, 1>();
+    default: return regs_of<256, 2>();
     }
 }

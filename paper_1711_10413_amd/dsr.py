@@ -51,7 +51,7 @@ EXPORTS = ("dsr_init", "dsr_destroy", "dsr_region_begin", "dsr_push", "dsr_publi
            "dsr_batch_launch_each", "dsr_batch_sync", "dsr_batch_result", "dsr_batch_times",
            "dsr_batch_elapsed", "dsr_batch_free", "dsr_autotune", "dsr_batch_replay_serial",
            "dsr_serve_start", "dsr_serve_submit", "dsr_serve_poll", "dsr_serve_pending",
-           "dsr_serve_replay", "dsr_serve_stop")
+           "dsr_serve_replay", "dsr_serve_stop", "dsr_occupancy_model", "dsr_region_occupancy")
 
 
 class dsr_config(C.Structure):
@@ -95,6 +95,27 @@ class dsr_done(C.Structure):
             fx.append(_fixed([w[0], w[1], w[2]]))
         return {"ticket": self.ticket, "status": self.status, "f64": list(self.f64[:self.n_red]),
                 "i64": list(self.i64[:self.n_red]), "fixed": fx, "device_us": self.device_us}
+
+
+class dsr_hw_model(C.Structure):
+    _fields_ = [("compute_units", C.c_uint32), ("regs_per_cu", C.c_uint32),
+                ("reg_granule", C.c_uint32), ("max_teams_per_cu", C.c_uint32),
+                ("max_threads_per_cu", C.c_uint32), ("shared_per_cu", C.c_uint32),
+                ("shared_granule", C.c_uint32), ("simds_per_cu", C.c_uint32),
+                ("wave_size", C.c_uint32)]
+
+
+class dsr_occupancy_t(C.Structure):
+    _fields_ = [("teams_per_cu", C.c_uint32), ("teams_by_registers", C.c_uint32),
+                ("teams_by_shared", C.c_uint32), ("teams_by_threads", C.c_uint32),
+                ("limiter", C.c_uint32), ("shared_per_team", C.c_uint32),
+                ("shared_per_cu", C.c_uint64), ("regs_per_thread", C.c_uint32),
+                ("hip_teams_per_cu", C.c_uint32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["limiter"] = ("teams", "registers", "shared", "threads")[self.limiter]
+        return d
 
 
 class DsrError(RuntimeError):
@@ -159,6 +180,9 @@ def lib():
                                  C.POINTER(P), i32, C.c_double, C.POINTER(C.c_double),
                                  C.POINTER(dsr_done)],
             "dsr_serve_stop": [P],
+            "dsr_occupancy_model": [C.POINTER(dsr_hw_model), u32, u32, u32,
+                                    C.POINTER(dsr_occupancy_t)],
+            "dsr_region_occupancy": [P, u32, C.POINTER(dsr_occupancy_t)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -420,6 +444,20 @@ def dsr_serve_replay(server, programs, prog, arrival_s, slot_outs=None, n_loops_
 
 def dsr_serve_stop(server):
     return _check(lib().dsr_serve_stop(server), "dsr_serve_stop")
+
+
+# ---- footprint and occupancy model --------------------------------------------
+def dsr_occupancy(hw, threads_per_team, regs_per_thread, shared_per_team):
+    o = dsr_occupancy_t()
+    _check(lib().dsr_occupancy_model(C.byref(hw), threads_per_team, regs_per_thread,
+                                     shared_per_team, C.byref(o)), "dsr_occupancy_model")
+    return o.as_dict()
+
+
+def dsr_region_occupancy(ctx, variant=0):
+    o = dsr_occupancy_t()
+    _check(lib().dsr_region_occupancy(ctx, variant, C.byref(o)), "dsr_region_occupancy")
+    return o.as_dict()
 
 
 # ---- frame images for the bodies' layouts (include/dsr.h) -----------------

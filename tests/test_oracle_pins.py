@@ -33,6 +33,13 @@ def test_counter_draws_match_sequential_generator():
         assert [int(v) for v in W.draws(seed, stream, 17, 5)] == seq[17:22]
 
 
+def test_fast_fp32_path_matches_numpy_path():
+    for seed, stream, start, count in [(1, 2, 0, 100000), (3, 515, 12345, 3 << 20), (4, 9, 7, 1)]:
+        a = W.uniform_f32(W.draws(seed, stream, start, count))
+        b = W.uniform_f32_draws(seed, stream, start, count)
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
 def test_value_maps_are_exact_and_in_range():
     u = W.draws(9, 2, 0, 200000)
     x = W.uniform_f32(u)
