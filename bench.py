@@ -67,29 +67,34 @@ def build_sweep(D, ctx, xs, ys, ks, W, schedule=0):
 
 
 def time_sweep(torch, D, regions, ks, steps, warmup, stream):
-    """Warmup + timed steps.  One HIP event between consecutive launches on
-    the launch stream: a kernel's duration is bounded by the gap between the
-    events around it."""
+    """Warmup, then the timed region: for each K its `steps` launches back
+    to back (buffer sets rotating), with one HIP event on the launch stream
+    after each K's group; a launch's duration is its group's time / steps."""
     cur = torch.cuda.current_stream()
     for w in range(warmup):
         for K in ks:
             D.dsr_launch(regions[(K, w % SETS)], stream)
     torch.cuda.synchronize()
     evs = [torch.cuda.Event(enable_timing=True)]
-    order = []
     t0 = time.perf_counter()
     evs[0].record(cur)
-    for st in range(steps):
-        for K in ks:
+    for K in ks:
+        for st in range(steps):
             D.dsr_launch(regions[(K, st % SETS)], stream)
-            e = torch.cuda.Event(enable_timing=True)
-            e.record(cur)
-            evs.append(e)
-            order.append(K)
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(cur)
+        evs.append(e)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
-    per = [(K, evs[i].elapsed_time(evs[i + 1])) for i, K in enumerate(order)]
-    return secs, per
+    per_k = {K: evs[i].elapsed_time(evs[i + 1]) / steps for i, K in enumerate(ks)}
+    return secs, per_k
+
+
+def kernel_variant(K):
+    """Compiled variant of the region kernel a K-scalar sweep region runs
+    (fixed chains up to 8+8 in variant 0, 16+16 in 1, 32+32 in 2)."""
+    ni, nf = (K + 1) // 2, K // 2
+    return 0 if max(ni, nf) <= 8 else (1 if max(ni, nf) <= 16 else 2)
 
 
 def run_sweep(torch, np, D, W, args, stream):
@@ -103,15 +108,19 @@ def run_sweep(torch, np, D, W, args, stream):
     ctx = D.dsr_init(wg_size=WG, lds_slab_bytes=4096, hbm_slab_bytes=4096, max_teams=TEAMS,
                      master_joins=args.master_joins, flags=D.DSR_F_TRACE)
     regions = build_sweep(D, ctx, xs, ys, ks, W, sched)
-    secs, per = time_sweep(torch, D, regions, ks, args.steps, args.warmup, stream)
+    secs, by_k = time_sweep(torch, D, regions, ks, args.steps, args.warmup, stream)
     n_regions = args.steps * len(ks)
-    avg_ms = sum(ms for _, ms in per) / len(per)
-    by_k = {K: float(np.mean([ms for k, ms in per if k == K])) for K in ks}
-    loop_us = {}
+    loop_us, phases = {}, {}
     for K in ks:
         r = regions[(K, (args.steps - 1) % SETS)]
         tr = [D.dsr_region_trace(r, t) for t in range(TEAMS)]
         loop_us[K] = (max(t["t_end"] for t in tr) - min(t["t_start"] for t in tr)) / 100.0
+        base = min(t["t_team"] for t in tr)
+
+        def late(key, mask=0xFFFFFFFF):
+            return max(((t[key] & mask) - base) & 0xFFFFFFFF for t in tr) / 100.0
+        phases[K] = {"last_release": late("t_start"), "last_join": late("t_end"),
+                     "last_program_end": late("t_program_end"), "last_arrival": late("t_arrived")}
     verified = None
     if not args.no_verify:
         from oracle import ref as R
@@ -133,8 +142,7 @@ def run_sweep(torch, np, D, W, args, stream):
                           master_joins=args.master_joins)
         regions2 = build_sweep(D, ctx2, xs, ys, ks, W, sched)
         secs2, per2 = time_sweep(torch, D, regions2, ks, args.steps, args.warmup, stream)
-        hbm_only = {"regions_per_s": n_regions / secs2,
-                    "kernel_ms_avg": sum(ms for _, ms in per2) / len(per2)}
+        hbm_only = {"regions_per_s": n_regions / secs2, "per_k_kernel_ms": per2}
         for r in regions2.values():
             D.dsr_region_free(r)
         D.dsr_destroy(ctx2)
@@ -145,13 +153,120 @@ def run_sweep(torch, np, D, W, args, stream):
     torch.cuda.empty_cache()
     algo = BYTES_PER_ELEM * N
     return {
-        "value": n_regions / secs, "secs": secs, "avg_ms": avg_ms, "algo_bytes": algo,
+        "value": n_regions / secs, "secs": secs, "algo_bytes": algo,
         "per_k_kernel_ms": by_k,
         "per_k_gbs": {K: algo / (ms * 1e-3) / 1e9 for K, ms in by_k.items()},
         "loop_phase_us": loop_us,
         "loop_phase_gbs": {K: algo / (us * 1e-6) / 1e9 for K, us in loop_us.items()},
+        "team_phases_us": phases,
         "lds_bytes_per_team": 704 + 4096, "hbm_only_stack": hbm_only, "verified": verified,
     }
+
+
+# ---- HBM traffic from counters --------------------------------------------------
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dsr_region_kernel_sweep_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1711_10413_amd", "csrc", "dsr_kernels.hip"),
+                  os.path.join(ROOT, "paper_1711_10413_amd", "csrc", "dsr_internal.h"),
+                  os.path.join(ROOT, "include", "dsr_device.h")]
+CALIB_N = 1 << 24            # calibration copy: fp32[2^24] -> fp64[2^24]
+CALIB_REPS = 4
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name):
+    """HBM bytes per launch of kernel `name` from the committed counter
+    summary, or None when there is none or the kernel source changed since
+    the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            line = line.strip().lstrip("-").strip()
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("kernel") != name:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def run_calib(torch):
+    """A plain conversion copy of known size (4 B read + 8 B written per
+    element, the sweep's own mix): its counter readings scale FETCH_SIZE and
+    WRITE_SIZE to bytes."""
+    x = torch.zeros(CALIB_N, dtype=torch.float32, device="cuda")
+    y = torch.empty(CALIB_N, dtype=torch.float64, device="cuda")
+    for _ in range(CALIB_REPS):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    return {"elements": CALIB_N, "reps": CALIB_REPS, "read_bytes": 4 * CALIB_N, "write_bytes": 8 * CALIB_N}
+
+
+def traffic_from_counters(fetch_csv, write_csv, fetch_cmd, write_cmd):
+    """Turn two rocprofv3 counter-collection CSVs (FETCH_SIZE, WRITE_SIZE, KiB
+    per dispatch) into the committed traffic summary: the region kernel's
+    mean per-launch readings, scaled by what the same counters read for the
+    calibration copy of known size."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        vals = {}
+        with open(path, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+        return vals
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    cal = [k for k in fetch if "copy" in k.lower() and "rocclr" not in k.lower()
+           and len(fetch[k]) == CALIB_REPS]
+    if len(cal) != 1:
+        raise SystemExit("calibration copy kernel not found uniquely: %s" % cal)
+    cal = cal[0]
+    f_scale = 4 * CALIB_N / (1024 * statistics.mean(fetch[cal]))
+    w_scale = 8 * CALIB_N / (1024 * statistics.mean(write[cal]))
+    name = "dsr_region_kernel<256, 0>"
+    keys = [k for k in fetch if k.startswith("void dsr_region_kernel<256, 0>")]
+    if len(keys) != 1:
+        raise SystemExit("region kernel not found: %s" % keys)
+    fk = statistics.mean(fetch[keys[0]]) * 1024 * f_scale
+    wk = statistics.mean(write[keys[0]]) * 1024 * w_scale
+    lines = [
+        "# HBM traffic of %s on the scalar sweep (K <= 16 regions)" % name, "",
+        "Per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) from two rocprofv3 counter runs,",
+        "each scaled by the same counter's reading for a plain fp32 -> fp64 copy of",
+        "2^24 elements (64 MiB read, 128 MiB written) in the same process.", "",
+        "fetch run: `%s`" % fetch_cmd, "", "write run: `%s`" % write_cmd, "",
+        "| kernel | dispatches | FETCH_SIZE KiB (mean) | WRITE_SIZE KiB (mean) |",
+        "|---|---|---|---|"]
+    for k in sorted(fetch):
+        if k in write:
+            lines.append("| %s | %d | %.1f | %.1f |" % (k[:80], len(fetch[k]), statistics.mean(fetch[k]),
+                                                      statistics.mean(write[k])))
+    lines += ["",
+              "- calibration_read_scale: %.4f" % f_scale,
+              "- calibration_write_scale: %.4f" % w_scale,
+              "- algorithmic_bytes_per_launch: %d" % (BYTES_PER_ELEM * N),
+              "- kernel: %s" % name,
+              "- fetch_bytes_per_launch: %.0f" % fk,
+              "- write_bytes_per_launch: %.0f" % wk,
+              "- traffic_bytes_per_launch: %.0f" % (fk + wk),
+              "- kernel_source_sha256: %s" % kernel_source_hash(), ""]
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
 
 
 # ---- plain region -------------------------------------------------------------
@@ -436,7 +551,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--parts", default="sweep,plain,arrays,batched,served,cpu",
-                    help="comma list of: sweep plain arrays batched served cpu")
+                    help="comma list of: sweep plain arrays batched served cpu calib")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-hbm-only", action="store_true")
     ap.add_argument("--master-joins", type=int, default=0)
@@ -444,7 +559,12 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of each served arrival schedule (the full workload is 60)")
     ap.add_argument("--serve-rates", default="1000,10000,50000")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_CMD", "WRITE_CMD"),
+                    help="write the HBM traffic summary from two counter runs and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from_counters(*args.traffic_from)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (a region would "
               "split by team blocks with one exact partial exchanged per GPU)", file=sys.stderr)
@@ -473,15 +593,27 @@ def main():
         sw = run_sweep(torch, np, D, W, args, stream)
         out["value"] = sw["value"]
         out["ms_per_step"] = sw["secs"] * 1e3 / args.steps
-        achieved = sw["algo_bytes"] / (sw["avg_ms"] * 1e-3) / 1e9
+        # the dominant kernel: the compiled variant with the most time in a step
+        ks = list(W.CFG2_KS)
+        share = {}
+        for K in ks:
+            share.setdefault(kernel_variant(K), []).append(K)
+        dom = max(share, key=lambda v: sum(sw["per_k_kernel_ms"][K] for K in share[v]))
+        avg_ms = sum(sw["per_k_kernel_ms"][K] for K in share[dom]) / len(share[dom])
+        achieved = sw["algo_bytes"] / (avg_ms * 1e-3) / 1e9
+        name = "dsr_region_kernel<256, %d>" % dom
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                           "kernel": "dsr_region_kernel",
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": measured_traffic(name),
+                           "kernel": name, "regions": "K in %s" % share[dom],
                            "algorithmic_bytes_per_launch": sw["algo_bytes"],
-                           "avg_launch_ms": sw["avg_ms"]}
+                           "avg_launch_ms": avg_ms}
         for k in ("per_k_kernel_ms", "per_k_gbs", "loop_phase_us", "loop_phase_gbs",
-                  "lds_bytes_per_team", "hbm_only_stack", "verified"):
+                  "team_phases_us", "lds_bytes_per_team", "hbm_only_stack", "verified"):
             out[k] = sw[k]
+    if "calib" in parts:
+        say("calib")
+        out["calibration_copy"] = run_calib(torch)
     if "plain" in parts:
         say("plain")
         out["plain_region"] = run_plain(torch, np, D, W, stream)

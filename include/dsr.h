@@ -209,6 +209,9 @@ int dsr_region_reduction(dsr_region *r, int32_t index, int64_t *i64, double *f64
  *                         workers were released for the first publish
  *   [84 .. 85]            wall clock when the last publish joined
  *   [86]                  low word of the wall clock at team start
+ *   [87], [88]            low words of the wall clock when the team's
+ *                         program ended and when its arrival (and, for the
+ *                         last team, the cross-team combine) was done
  *   [96 + 2w, 97 + 2w]    low words of the wall clock when wave w started
  *                         and finished its share of the last body it ran   */
 #define DSR_TRACE_WORDS 128

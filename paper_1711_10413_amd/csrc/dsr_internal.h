@@ -97,7 +97,9 @@ struct dsr_dlaunch {
     const uint32_t *items;  /* [n_items][2] = {region, team}, or null */
     uint32_t n_items;
     uint32_t n_regions;
-    uint32_t *counter;      /* [0] next item, [1] workgroups finished */
+    uint32_t *counter;      /* [0] next item, [1] workgroups finished;
+                               served form: [16] device copy of the published
+                               count, [32] device copy of the stop flag */
     uint64_t *done_ts;      /* per region: wall clock when its result was written;
                                [n_regions]: when item 0 was claimed */
     /* served form (published != null): items arrive over time in a ring */

@@ -380,26 +380,165 @@ __device__ __forceinline__ void body_fma_fixed(const uint8_t *fb, const dsr_dloo
     for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_span<NI, NF>(s, x, y, q, A); });
 }
 
-/* fma chain with run-time scalar counts and an optional shared array:
- * the scalars are read from the frame (LDS broadcast or scalar-cache
- * loads) on every use. */
-__device__ __forceinline__ void fma_generic_span(const uint8_t *fb, const dsr_dloop &L, span_t sp,
-                                                 lane_acc &A)
+/* fma chain with a run-time scalar count n <= 64 and an optional shared
+ * int32 array (the chain then starts from the array element).  Lane k of
+ * the wave holds scalar k as a double (`sv`); each step of the chain takes
+ * it with two readlanes into scalar registers, shared by all the elements
+ * of a batch.  The array index i mod alen is carried from element to
+ * element (one conditional subtraction per step) instead of divided.  The
+ * element layout, batching and software pipelining are those of fma_span. */
+__device__ __forceinline__ double readlane_f64(double v, uint32_t k)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, k);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), k);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ uint32_t mod_step(uint32_t j, uint32_t d, uint32_t m)
+{
+    j += d;
+    return j >= m ? j - m : j;
+}
+
+template <int U, class AP>
+__device__ __forceinline__ void rt_chain(double sv, uint32_t n, double (&acc)[2 * U], const double (&xd)[2 * U])
+{
+    for (uint32_t k = 0; k < n; ++k) {
+        const double sk = readlane_f64(sv, k);
+#pragma unroll
+        for (int e = 0; e < 2 * U; ++e) acc[e] = __builtin_fma(sk, xd[e], acc[e]);
+    }
+}
+
+template <bool ARR, class AP>
+__device__ __forceinline__ double rt_one(double sv, uint32_t n, AP arr, uint32_t alen, double xd, uint64_t i)
+{
+    double acc = 0.0;
+    if constexpr (ARR) acc = (double)arr[(uint32_t)(i % alen)];
+    for (uint32_t k = 0; k < n; ++k) acc = __builtin_fma(readlane_f64(sv, k), xd, acc);
+    return acc;
+}
+
+template <int U, bool ARR, class AP>
+__device__ __forceinline__ void fma_rt_span(double sv, uint32_t n, AP arr, uint32_t alen,
+                                            const GLB float *__restrict__ x, GLB double *__restrict__ y,
+                                            span_t sp, lane_acc &A)
+{
+    const uint64_t plo = min(sp.hi, (sp.lo + 1) & ~1ull);
+    const uint64_t phi = max(plo, sp.hi & ~1ull);
+    if (sp.lo < plo && sp.p == 0) {
+        const double v = rt_one<ARR>(sv, n, arr, alen, (double)x[sp.lo], sp.lo);
+        y[sp.lo] = v;
+        acc_add_f64(A, v);
+    }
+    lane_acc Ac[2] = {acc_zero(), acc_zero()};
+    const GLB f32x2 *__restrict__ x2 = (const GLB f32x2 *)x;
+    GLB f64x2 *__restrict__ y2 = (GLB f64x2 *)y;
+    const uint64_t nv1 = phi >> 1;
+    const uint64_t step = (uint64_t)U * sp.P;
+    uint64_t v = (plo >> 1) + sp.p;
+    /* array index of element 2v and its advance per pair stride */
+    uint32_t j = 0, dj = 0;
+    if constexpr (ARR) {
+        j = (uint32_t)((2 * v) % alen);
+        dj = (uint32_t)((2ull * sp.P) % alen);
+    }
+    if (v + (uint64_t)(U - 1) * sp.P < nv1) {
+        f32x2 cur[U];
+        int32_t ca[2 * U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) cur[u] = __builtin_nontemporal_load(&x2[v + (uint64_t)u * sp.P]);
+        if constexpr (ARR) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                ca[2 * u] = arr[j];
+                ca[2 * u + 1] = arr[j + 1 == alen ? 0 : j + 1];
+                j = mod_step(j, dj, alen);
+            }
+        }
+        for (;;) {
+            const uint64_t vn = v + step;
+            const bool more = vn + (uint64_t)(U - 1) * sp.P < nv1;
+            f32x2 nxt[U];
+            int32_t na[2 * U];
+            if (more) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) nxt[u] = __builtin_nontemporal_load(&x2[vn + (uint64_t)u * sp.P]);
+                if constexpr (ARR) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        na[2 * u] = arr[j];
+                        na[2 * u + 1] = arr[j + 1 == alen ? 0 : j + 1];
+                        j = mod_step(j, dj, alen);
+                    }
+                }
+            }
+            double xd[2 * U], acc[2 * U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                xd[2 * u] = (double)cur[u].x;
+                xd[2 * u + 1] = (double)cur[u].y;
+                acc[2 * u] = ARR ? (double)ca[2 * u] : 0.0;
+                acc[2 * u + 1] = ARR ? (double)ca[2 * u + 1] : 0.0;
+            }
+            rt_chain<U, AP>(sv, n, acc, xd);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                f64x2 r;
+                r.x = acc[2 * u];
+                r.y = acc[2 * u + 1];
+                __builtin_nontemporal_store(r, &y2[v + (uint64_t)u * sp.P]);
+                acc_add_f64(Ac[0], r.x);
+                acc_add_f64(Ac[1], r.y);
+            }
+            v = vn;
+            if (!more) break;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                cur[u] = nxt[u];
+                if constexpr (ARR) {
+                    ca[2 * u] = na[2 * u];
+                    ca[2 * u + 1] = na[2 * u + 1];
+                }
+            }
+        }
+    }
+    for (; v < nv1; v += sp.P) {
+        const f32x2 xv = __builtin_nontemporal_load(&x2[v]);
+        f64x2 r;
+        r.x = rt_one<ARR>(sv, n, arr, alen, (double)xv.x, 2 * v);
+        r.y = rt_one<ARR>(sv, n, arr, alen, (double)xv.y, 2 * v + 1);
+        __builtin_nontemporal_store(r, &y2[v]);
+        acc_add_f64(Ac[0], r.x);
+        acc_add_f64(Ac[1], r.y);
+    }
+    if (phi < sp.hi && sp.p == 0) {
+        const double r = rt_one<ARR>(sv, n, arr, alen, (double)x[phi], phi);
+        y[phi] = r;
+        acc_add_f64(A, r);
+    }
+    acc_merge(A, Ac[0]);
+    acc_merge(A, Ac[1]);
+}
+
+/* Body entry for the run-time chain: every lane loads its scalar (lane k
+ * < ni: int32 scalar k; ni <= k < ni + nf: fp64 scalar k - ni) once, then
+ * the loop streams, U element pairs per lane and batch. */
+template <int U, class AP>
+__device__ __forceinline__ void body_fma_rt(const uint8_t *fb, AP arr, const dsr_dloop &L, span_t sp,
+                                            lane_acc &A, uint32_t *claim, uint32_t lane)
 {
     const uint32_t ni = L.ni, nf = L.nf, alen = L.alen;
-    const double *sf = (const double *)(fb + 24);
-    const int32_t *si = (const int32_t *)(fb + 24 + 8 * nf);
-    const int32_t *arr = (const int32_t *)(fb + ((24 + 8 * nf + 4 * ni + 15) & ~15u));
-    const GLB float *__restrict__ x = (const GLB float *)L.in;
-    GLB double *__restrict__ y = (GLB double *)L.out;
-    for (uint64_t i = sp.lo + sp.p; i < sp.hi; i += sp.P) {
-        const double xd = (double)x[i];
-        double acc = alen ? (double)arr[i % alen] : 0.0;
-        for (uint32_t k = 0; k < ni; ++k) acc = __builtin_fma((double)si[k], xd, acc);
-        for (uint32_t k = 0; k < nf; ++k) acc = __builtin_fma(sf[k], xd, acc);
-        y[i] = acc;
-        acc_add_f64(A, acc);
-    }
+    double sv = 0.0;
+    if (lane < ni) sv = (double)*(const int32_t *)(fb + 24 + 8 * nf + 4 * lane);
+    else if (lane < ni + nf) sv = *(const double *)(fb + 24 + 8 * (lane - ni));
+    const GLB float *x = (const GLB float *)L.in;
+    GLB double *y = (GLB double *)L.out;
+    if (alen)
+        for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_rt_span<U, true>(sv, ni + nf, arr, alen, x, y, q, A); });
+    else
+        for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_rt_span<U, false>(sv, ni + nf, arr, alen, x, y, q, A); });
 }
 
 /* Shared-array gather; arrays at `arr` (LDS or global pointer), `len`
@@ -529,9 +668,10 @@ __device__ __forceinline__ const uint8_t *frame_ptr(const team_t &T, frame_t f)
 /* VARIANT selects which fixed-length fma chains are compiled into the
  * kernel: the worker code is specialised to the bodies a region can
  * publish, so a region of short chains does not pay the register budget
- * of the longest one.  0: chains up to 8+8 scalars; 1: adds 16+16;
- * 2: adds 32+32; -1 (workgroups above 256 threads, 128 registers per
- * lane): run-time loop only.  Other lengths use the run-time loop. */
+ * of the longest one.  0: chains up to 8+8 scalars (workgroups of up to
+ * 512 threads); 1: adds 16+16; 2: adds 32+32; -1 (workgroups above 512
+ * threads, 128 registers per lane): run-time chains only.  Other lengths
+ * (at most 64 scalars) use the run-time chain, one pair per batch at -1. */
 template <int VARIANT>
 __device__ __forceinline__ void run_body(team_t &T, uint32_t body, frame_t f, const dsr_dloop &L, span_t sp,
                                          lane_acc &A, uint32_t *claim, uint32_t member,
@@ -561,7 +701,14 @@ __device__ __forceinline__ void run_body(team_t &T, uint32_t body, frame_t f, co
             if constexpr (VARIANT >= 2)
                 if (ni == 32 && nf == 32) { body_fma_fixed<32, 32>(fb, L, sp, A, claim, lane); break; }
         }
-        for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_generic_span(fb, L, q, A); });
+        /* run-time chain (the host admits at most 64 scalars); workgroups
+         * above 512 threads have 128 registers per lane */
+        const uint32_t aoff = (24 + 8 * nf + 4 * ni + 15) & ~15u;
+        constexpr int U = VARIANT < 0 ? 1 : 4;
+        if (f.space == SPACE_LDS)
+            body_fma_rt<U>(fb, (const LDSQ int32_t *)(dsr_lds + cb_bytes(T.nw) + f.off + aoff), L, sp, A, claim, lane);
+        else
+            body_fma_rt<U>(fb, (const GLB int32_t *)(frame_hbm(T, f) + aoff), L, sp, A, claim, lane);
         break;
     }
     case DSR_BODY_GATHER: {
@@ -671,6 +818,45 @@ __device__ __forceinline__ void init_frame(team_t &T, frame_t f, const uint8_t *
     for (uint32_t o = nvec * 16 + T.lane; o < nbytes; o += 64) dst[o] = o < init_bytes ? src[o] : 0;
 }
 
+/* The region's program, one op per lane of the master wave: all ops are
+ * loaded in one round trip when the program starts, and each step takes
+ * its op with readlanes, so no op load waits behind the parallel region. */
+struct op_lanes {
+    uint32_t w[10];
+};
+
+__device__ __forceinline__ op_lanes load_ops(const dsr_op *ops, uint32_t n, uint32_t lane)
+{
+    op_lanes o;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) o.w[i] = 0;
+    if (lane < n) {
+        const uint4 *p = (const uint4 *)(ops + lane);
+        const uint4 a = p[0], b = p[1], c = p[2];
+        o.w[0] = a.x; o.w[1] = a.y; o.w[2] = a.z; o.w[3] = a.w;
+        o.w[4] = b.x; o.w[5] = b.y; o.w[6] = b.z; o.w[7] = b.w;
+        o.w[8] = c.x; o.w[9] = c.y;
+    }
+    return o;
+}
+
+__device__ __forceinline__ dsr_op op_at(const op_lanes &o, uint32_t k)
+{
+    dsr_op op;
+    op.kind = __builtin_amdgcn_readlane(o.w[0], k);
+    op.frame = __builtin_amdgcn_readlane(o.w[1], k);
+    op.nbytes = __builtin_amdgcn_readlane(o.w[2], k);
+    op.init_bytes = __builtin_amdgcn_readlane(o.w[3], k);
+    op.init_stride = __builtin_amdgcn_readlane(o.w[4], k);
+    op.body = __builtin_amdgcn_readlane(o.w[5], k);
+    op.loop = __builtin_amdgcn_readlane(o.w[6], k);
+    op.red = __builtin_amdgcn_readlane(o.w[7], k);
+    op.init_off = (uint64_t)__builtin_amdgcn_readlane(o.w[8], k) |
+                  ((uint64_t)__builtin_amdgcn_readlane(o.w[9], k) << 32);
+    op.pad = 0;
+    return op;
+}
+
 /* Master wave: the sequential code block of one region for one team
  * (Figure 2): pushes, publishes and pops.  Returns the team's error. */
 template <int VARIANT>
@@ -686,8 +872,12 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
     uint32_t npush = 0;
     bool stamped = false;
     const uint32_t nwork = C.master_joins ? T.nw : T.nw - 1;
-    for (uint32_t k = 0; k < R.n_ops; ++k) {
-        const dsr_op op = R.ops[k];
+    const uint32_t n_ops = min(uniform(R.n_ops), (uint32_t)DSR_MAX_OPS);
+    /* the 1024-thread instance has no registers to spare: it reads each op
+     * when it gets to it */
+    const op_lanes prog = load_ops(R.ops, VARIANT < 0 ? 0 : n_ops, T.lane);
+    for (uint32_t k = 0; k < n_ops; ++k) {
+        const dsr_op op = VARIANT < 0 ? R.ops[k] : op_at(prog, k);
         if (op.kind == DSR_OP_PUSH) {
             const frame_t f = push(T, op.nbytes);
             if (f.space == SPACE_NONE) { err = DSR_E_NOMEM; break; }
@@ -786,16 +976,35 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
     return err;
 }
 
-/* Last team: combine every team's partials, in 192-bit integers. */
-__device__ __forceinline__ void combine_teams(const dsr_dregion &R, uint32_t lane)
+/* Sum `cnt` 192-bit partials (three words each, `stride` partials apart)
+ * with the whole wave: each lane issues up to four independent loads per
+ * round, so a group of up to 256 partials costs one memory round trip. */
+__device__ __forceinline__ i192 sum_partials(const uint64_t *base, uint32_t cnt, uint32_t stride, uint32_t lane)
+{
+    i192 s{0, 0, 0};
+    for (uint32_t j0 = 0; j0 < cnt; j0 += 256) {
+        uint64_t w[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t j = j0 + 64u * u + lane;
+            const uint64_t *pp = base + 3ull * j * stride;
+            const bool in = j < cnt;
+            w[u][0] = in ? load_dev(pp) : 0;
+            w[u][1] = in ? load_dev(pp + 1) : 0;
+            w[u][2] = in ? load_dev(pp + 2) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s = add192(s, i192{w[u][0], w[u][1], w[u][2]});
+    }
+    return wave_sum192(s);
+}
+
+/* Last team: the region's reductions from the (group) partials, exact in
+ * 192-bit integers, rounded once for fp64. */
+__device__ __forceinline__ void combine_teams(const dsr_dregion &R, uint32_t cnt, uint32_t stride, uint32_t lane)
 {
     for (uint32_t r = 0; r < R.n_red; ++r) {
-        i192 s{0, 0, 0};
-        for (uint32_t t = lane; t < R.teams; t += 64) {
-            const uint64_t *pp = R.partials + ((uint64_t)r * R.teams + t) * 3;
-            s = add192(s, i192{load_dev(pp), load_dev(pp + 1), load_dev(pp + 2)});
-        }
-        s = wave_sum192(s);
+        const i192 s = sum_partials(R.partials + (uint64_t)r * R.teams * 3, cnt, stride, lane);
         if (lane == 0) {
             R.result->fixed[r][0] = s.w0;
             R.result->fixed[r][1] = s.w1;
@@ -825,10 +1034,11 @@ __device__ __forceinline__ void publish_record(const dsr_dregion &R, dsr_drec *r
     __hip_atomic_store(&rec->seq, R.tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-/* A team's arrival after its program: the last team of the region
- * combines the partials.  Arrivals go through a two-level tree (groups of
- * teams, then groups) so that no counter sees more than a few dozen
- * simultaneous atomics. */
+/* A team's arrival after its program.  Arrivals go through a two-level
+ * tree (groups of teams, then groups) so that no counter sees more than a
+ * few dozen simultaneous atomics; the last team of a group adds up the
+ * group's partials and leaves the sum in the group's first partial slot,
+ * and the last group's leader combines the group sums into the result. */
 __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team, uint32_t lane,
                                             uint64_t *done_ts, dsr_drec *rec = nullptr)
 {
@@ -844,6 +1054,16 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team,
     if (prev != in_group - 1) return;
     if (lane == 0) __hip_atomic_store(&R.result->group[g * 16], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (ngroups > 1) {
+        for (uint32_t r = 0; r < R.n_red; ++r) {
+            uint64_t *gp = R.partials + ((uint64_t)r * R.teams + (uint64_t)g * gsize) * 3;
+            const i192 s = sum_partials(gp, in_group, 1, lane);
+            if (lane == 0) {
+                store_dev(gp, s.w0);
+                store_dev(gp + 1, s.w1);
+                store_dev(gp + 2, s.w2);
+            }
+        }
+        drain_memory();                  /* the group sums are stored */
         if (lane == 0)
             prev = __hip_atomic_fetch_add(&R.result->arrived, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         prev = uniform((uint32_t)__shfl((int)prev, 0, 64));
@@ -852,7 +1072,8 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team,
     }
     int32_t err = 0;
     if (lane == 0) err = __hip_atomic_exchange(&R.result->error, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    combine_teams(R, lane);
+    if (ngroups > 1) combine_teams(R, ngroups, gsize, lane);
+    else combine_teams(R, R.teams, 1, lane);
     if (lane < DSR_MAX_LOOPS)
         __hip_atomic_store(&R.result->claim[lane], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (lane == 0) {
@@ -863,24 +1084,64 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team,
     if (rec) publish_record(R, rec, lane);
 }
 
-/* Served form: lane 0 polls the host's published count (system-scope
- * acquire) with short sleeps.  Returns true once item `it` is published;
- * false when the host asked to stop or nothing arrived for idle_limit
- * ticks, so every wave reaches an exit. */
+/* Served form: wait until item `it` is published.  The host's published
+ * count lives in host memory, so polling it crosses PCIe; only the
+ * workgroup holding the next unpublished item (it == the device copy of
+ * the count) polls the host, and it mirrors what it sees into device
+ * memory, where every other waiting workgroup polls.  Polls are relaxed
+ * (an acquire per poll would invalidate the L2 each time) and back off
+ * with sleeps; once the item is seen, one agent-scope acquire makes the
+ * request's device-memory inputs visible.  Returns false when the host
+ * asked to stop or nothing arrived for idle_limit ticks, so every wave
+ * reaches an exit. */
 __device__ __forceinline__ bool wait_published(const dsr_dlaunch &LP, uint32_t it, uint32_t lane)
 {
     uint32_t ok = 0;
     if (lane == 0) {
+        uint32_t *dpub = LP.counter + 16, *dstop = LP.counter + 32;
         const uint64_t t0 = wall_clock64();
+        uint32_t nap = 0;
         for (;;) {
-            const uint32_t pub = __hip_atomic_load(LP.published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+            const uint32_t pub = __hip_atomic_load(dpub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (it < pub) { ok = 1; break; }
-            if (__hip_atomic_load(LP.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+            if (__hip_atomic_load(dstop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (it == pub) {
+                const uint32_t h = __hip_atomic_load(LP.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                if (h != pub) {
+                    __hip_atomic_fetch_max(dpub, h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 1;
+                    break;
+                }
+                if (__hip_atomic_load(LP.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+                    __hip_atomic_store(dstop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                nap = 0;
+            }
             if (wall_clock64() - t0 > LP.idle_limit) break;
-            __builtin_amdgcn_s_sleep(8);
+            /* s_sleep takes an immediate (64 * n clocks); workgroups whose
+             * item is far from the next one published sleep longest */
+            if (it - pub >= 64) {
+                __builtin_amdgcn_s_sleep(127);
+                __builtin_amdgcn_s_sleep(127);
+                __builtin_amdgcn_s_sleep(127);
+                __builtin_amdgcn_s_sleep(127);
+            } else {
+                switch (nap) {
+                case 0: __builtin_amdgcn_s_sleep(1); break;
+                case 1: __builtin_amdgcn_s_sleep(2); break;
+                case 2: __builtin_amdgcn_s_sleep(4); break;
+                case 3: __builtin_amdgcn_s_sleep(8); break;
+                case 4: __builtin_amdgcn_s_sleep(16); break;
+                default: __builtin_amdgcn_s_sleep(32); break;
+                }
+                if (nap < 5) ++nap;
+            }
         }
     }
-    return __shfl((int)ok, 0, 64) != 0;
+    ok = __shfl((int)ok, 0, 64);
+    if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok != 0;
 }
 
 /* Served form: the request slot's descriptor, program and loop
@@ -968,9 +1229,12 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
             }
             const dsr_dregion &R = C.serve ? stage_request(T, LP.regions + region) : LP.regions[region];
             run_program<VARIANT>(T, R, C, region, team, barriers, inner_pushes);
+            uint32_t *tr = (single && C.trace && R.trace) ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
+            if (tr && T.lane == 0) tr[87] = (uint32_t)wall_clock64();
             if (C.serve) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); /* outputs out of L2 */
             finish_team(R, team, T.lane, (LP.done_ts && !LP.published) ? LP.done_ts + region : nullptr,
                         LP.recs ? LP.recs + region : nullptr);
+            if (tr && T.lane == 0) tr[88] = (uint32_t)wall_clock64();
         }
         if (LP.exited && T.lane == 0)
             __hip_atomic_fetch_add(LP.exited, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1025,7 +1289,8 @@ extern "C" int dsr_launch_region_kernel(const dsr_dlaunch *lp, const dsr_dconfig
                                         void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    if (wg_size > 256) return (int)launch_variant<1024, -1>(lp, cfg, grid, wg_size, lds_bytes, s);
+    if (wg_size > 512) return (int)launch_variant<1024, -1>(lp, cfg, grid, wg_size, lds_bytes, s);
+    if (wg_size > 256) return (int)launch_variant<512, 0>(lp, cfg, grid, wg_size, lds_bytes, s);
     switch (variant) {
     case 0: return (int)launch_variant<256, 0>(lp, cfg, grid, wg_size, lds_bytes, s);
     case 1: return (int)launch_variant<256, 1>(lp, cfg, grid, wg_size, lds_bytes, s);
@@ -1047,7 +1312,8 @@ static int occupancy_of(uint32_t wg_size, uint32_t lds_bytes)
 
 extern "C" int dsr_region_kernel_occupancy(uint32_t wg_size, uint32_t lds_bytes, uint32_t variant)
 {
-    if (wg_size > 256) return occupancy_of<1024, -1>(wg_size, lds_bytes);
+    if (wg_size > 512) return occupancy_of<1024, -1>(wg_size, lds_bytes);
+    if (wg_size > 256) return occupancy_of<512, 0>(wg_size, lds_bytes);
     switch (variant) {
     case 0: return occupancy_of<256, 0>(wg_size, lds_bytes);
     case 1: return occupancy_of<256, 1>(wg_size, lds_bytes);
@@ -1065,7 +1331,8 @@ static int regs_of()
 
 extern "C" int dsr_region_kernel_regs(uint32_t wg_size, uint32_t variant)
 {
-    if (wg_size > 256) return regs_of<1024, -1>();
+    if (wg_size > 512) return regs_of<1024, -1>();
+    if (wg_size > 256) return regs_of<512, 0>();
     switch (variant) {
     case 0: return regs_of<256, 0>();
     case 1: return regs_of<256, 1>();

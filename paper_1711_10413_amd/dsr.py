@@ -283,7 +283,7 @@ def dsr_region_trace(region, team):
             "barriers": t[49:65], "inner_pushes": t[65:81],
             "error": C.c_int32(t[81]).value,
             "t_start": t[82] | (t[83] << 32), "t_end": t[84] | (t[85] << 32),
-            "t_team": t[86], "wave_loop": [(t[96 + 2 * w], t[97 + 2 * w]) for w in range(16)]}
+            "t_team": t[86], "t_program_end": t[87], "t_arrived": t[88], "wave_loop": [(t[96 + 2 * w], t[97 + 2 * w]) for w in range(16)]}
 
 
 def dsr_region_elapsed(region):

@@ -111,6 +111,13 @@ def test_publish_validation():
         assert e.value.code == D.DSR_E_INVAL, kw
     D.dsr_publish(r, f, D.DSR_BODY_GATHER, 8, out=0x1000, arrays=1, length=4)
     D.dsr_pop(r, f)
+    # a chain of more than 64 scalars is refused even when its frame is big enough
+    g = D.dsr_push(r, 24 + 8 * 64 + 4)
+    with pytest.raises(D.DsrError) as e:
+        D.dsr_publish(r, g, D.DSR_BODY_FMA_CHAIN, 8, inp=0x1000, out=0x2000, ni=1, nf=64)
+    assert e.value.code == D.DSR_E_INVAL
+    D.dsr_publish(r, g, D.DSR_BODY_FMA_CHAIN, 8, inp=0x1000, out=0x2000, ni=0, nf=64)
+    D.dsr_pop(r, g)
     D.dsr_region_free(r)
     D.dsr_destroy(ctx)
 

@@ -278,6 +278,58 @@ def test_generic_chain_with_array(inst, lds):
     D.dsr_destroy(ctx)
 
 
+def rt_inputs(ni, nf, alen, n, seed=5):
+    from dsr_workloads.gen import draws, uniform_int, uniform_f64
+    s_i = uniform_int(draws(seed, 0, 0, ni), -(1 << 20), 1 << 20).astype(np.int32)
+    s_f = uniform_f64(draws(seed, 1, 0, nf)) if nf else np.zeros(0)
+    arr = uniform_int(draws(seed, 16, 0, alen), 0, (1 << 16) - 1).astype(np.int32) if alen else None
+    return s_i, s_f, arr, W.uniform_f32_draws(seed, 2, 0, n)
+
+
+@pytest.mark.parametrize("ni,nf,alen,n,wg,teams,joins", [
+    (3, 2, 0, 100003, 256, 5, 0),        # odd count, no array, ragged tail
+    (2, 1, 1, 4099, 256, 3, 0),          # one-element array
+    (5, 4, 7, 65537, 256, 4, 1),         # odd array length, master joins
+    (32, 16, 1000, 70001, 256, 3, 0),    # the batched workload's common shape
+    (33, 31, 5, 50001, 256, 2, 0),       # 64 scalars: the run-time chain's limit
+    (4, 4, 384, 77777, 256, 3, 0),       # array length = pair stride of 3 waves
+    (4, 4, 385, 77777, 256, 3, 0),       # one past it
+    (16, 16, 96, 123457, 512, 3, 1),     # 512-thread workgroups
+    (32, 32, 0, 99999, 1024, 2, 0),      # 1024-thread workgroups, one pair per batch
+    (6, 3, 130, 3, 256, 2, 0),           # fewer elements than lanes
+])
+def test_runtime_chain_shapes(ni, nf, alen, n, wg, teams, joins):
+    """Run-time scalar counts with and without a shared array: array index
+    carried across batches, odd lengths, every workgroup size class."""
+    say("rt chain", ni, nf, alen, n, wg, teams, joins)
+    s_i, s_f, arr, x_np = rt_inputs(ni, nf, alen, n)
+    ctx = D.dsr_init(wg_size=wg, lds_slab_bytes=8192, hbm_slab_bytes=8192, max_teams=64,
+                     master_joins=joins)
+    x = torch.from_numpy(x_np).cuda()
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, r = fma_region(ctx, teams, s_i, s_f, x, y, arr=arr)
+    assert st == 0
+    check_fma(r, x_np, s_i, s_f, y, arr)
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+
+
+def test_runtime_chain_frame_in_hbm():
+    """The run-time chain with its frame (scalars and array) in the HBM slab."""
+    say("rt chain hbm frame")
+    s_i, s_f, arr, x_np = rt_inputs(20, 10, 333, 90001, seed=6)
+    ctx = D.dsr_init(wg_size=256, lds_slab_bytes=0, hbm_slab_bytes=4096, max_teams=64,
+                     flags=D.DSR_F_TRACE)
+    x = torch.from_numpy(x_np).cuda()
+    y = torch.zeros(x.numel(), dtype=torch.float64, device="cuda")
+    st, r = fma_region(ctx, 4, s_i, s_f, x, y, arr=arr)
+    assert st == 0
+    assert D.dsr_region_trace(r, 0)["placements"][0][0] == "hbm"
+    check_fma(r, x_np, s_i, s_f, y, arr)
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+
+
 def test_fma_wide_workgroup_and_empty():
     say("fma wg 1024, n 0")
     cf, x_np = W.cfg2_inputs(8, n=100003)
