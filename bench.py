@@ -106,21 +106,33 @@ def run_sweep(torch, np, D, W, args, stream):
     ys = [torch.empty(N, dtype=torch.float64, device=dev) for _ in range(SETS)]
     sched = 1 if args.schedule == "dynamic" else 0
     ctx = D.dsr_init(wg_size=WG, lds_slab_bytes=4096, hbm_slab_bytes=4096, max_teams=TEAMS,
-                     master_joins=args.master_joins, flags=D.DSR_F_TRACE)
+                     master_joins=args.master_joins)
     regions = build_sweep(D, ctx, xs, ys, ks, W, sched)
     secs, by_k = time_sweep(torch, D, regions, ks, args.steps, args.warmup, stream)
     n_regions = args.steps * len(ks)
     loop_us, phases = {}, {}
-    for K in ks:
-        r = regions[(K, (args.steps - 1) % SETS)]
-        tr = [D.dsr_region_trace(r, t) for t in range(TEAMS)]
-        loop_us[K] = (max(t["t_end"] for t in tr) - min(t["t_start"] for t in tr)) / 100.0
-        base = min(t["t_team"] for t in tr)
+    if not args.no_phases:
+        # after the timed region: one traced launch per K for the loop phase
+        # and the teams' phase stamps (tracing adds a few stores per team)
+        ctx_t = D.dsr_init(wg_size=WG, lds_slab_bytes=4096, hbm_slab_bytes=4096, max_teams=TEAMS,
+                           master_joins=args.master_joins, flags=D.DSR_F_TRACE)
+        traced = build_sweep(D, ctx_t, xs, ys, ks, W, sched)
+        for K in ks:
+            for s in range(2):
+                D.dsr_launch(traced[(K, s)], stream)
+            r = traced[(K, 1)]
+            D.dsr_region_sync(r)
+            tr = [D.dsr_region_trace(r, t) for t in range(TEAMS)]
+            loop_us[K] = (max(t["t_end"] for t in tr) - min(t["t_start"] for t in tr)) / 100.0
+            base = min(t["t_team"] for t in tr)
 
-        def late(key, mask=0xFFFFFFFF):
-            return max(((t[key] & mask) - base) & 0xFFFFFFFF for t in tr) / 100.0
-        phases[K] = {"last_release": late("t_start"), "last_join": late("t_end"),
-                     "last_program_end": late("t_program_end"), "last_arrival": late("t_arrived")}
+            def late(key, mask=0xFFFFFFFF):
+                return max(((t[key] & mask) - base) & 0xFFFFFFFF for t in tr) / 100.0
+            phases[K] = {"last_release": late("t_start"), "last_join": late("t_end"),
+                         "last_program_end": late("t_program_end"), "last_arrival": late("t_arrived")}
+        for r in traced.values():
+            D.dsr_region_free(r)
+        D.dsr_destroy(ctx_t)
     verified = None
     if not args.no_verify:
         from oracle import ref as R
@@ -157,9 +169,9 @@ def run_sweep(torch, np, D, W, args, stream):
         "per_k_kernel_ms": by_k,
         "per_k_gbs": {K: algo / (ms * 1e-3) / 1e9 for K, ms in by_k.items()},
         "loop_phase_us": loop_us,
-        "loop_phase_gbs": {K: algo / (us * 1e-6) / 1e9 for K, us in loop_us.items()},
+        "loop_phase_gbs": {K: algo / (us * 1e-6) / 1e9 for K, us in loop_us.items() if us > 0},
         "team_phases_us": phases,
-        "lds_bytes_per_team": 704 + 4096, "hbm_only_stack": hbm_only, "verified": verified,
+        "lds_bytes_per_team": D.dsr_control_bytes(WG) + 4096, "hbm_only_stack": hbm_only, "verified": verified,
     }
 
 
@@ -269,6 +281,62 @@ def traffic_from_counters(fetch_csv, write_csv, fetch_cmd, write_cmd):
     print("\n".join(lines))
 
 
+# ---- publish by reference list (section 5.2) ---------------------------------------
+def run_lists(torch, np, D, W, stream, reps=20):
+    """The sweep's fma chain published three ways, per launch: one frame
+    (this runtime's form), a list of references on chip (up to 20), and the
+    same list in global memory (DSR_F_GLOBAL_LISTS), at the sweep's size
+    and at a small size where per-region costs dominate."""
+    from oracle import ref as R
+    dev = torch.device("cuda:0")
+    out = {}
+    for n, teams in ((N, TEAMS), (1 << 16, 64)):
+        _, x_np = W.cfg2_inputs(1, n=n)
+        x = torch.from_numpy(x_np).to(dev)
+        y = torch.empty(n, dtype=torch.float64, device=dev)
+        rows = {}
+        for K in (8, 16, 38):
+            cf, _ = W.cfg2_inputs(K, n=n, with_x=False)
+            ni, nf = len(cf.s_i32), len(cf.s_f64)
+            img, size = D.fma_chain_frame(cf.s_i32, cf.s_f64)
+            refs = [(0, 0)] + [(0, 24 + 8 * nf + 4 * k) for k in range(ni)] + [(0, 24 + 8 * k) for k in range(nf)]
+            want = R.exact_sum(R.fma_chain(x_np, cf.s_i32, cf.s_f64))
+            row = {"references": len(refs)}
+            for mode, flags in (("frame", 0), ("list", 0), ("global_list", D.DSR_F_GLOBAL_LISTS)):
+                ctx = D.dsr_init(wg_size=WG, lds_slab_bytes=4096, hbm_slab_bytes=4096, max_teams=teams,
+                                 flags=flags | D.DSR_F_TRACE)
+                r = D.dsr_region_begin(ctx, teams)
+                f = D.dsr_push(r, size, img)
+                if mode == "frame":
+                    D.dsr_publish(r, f, D.DSR_BODY_FMA_CHAIN, n, inp=x.data_ptr(), out=y.data_ptr(), ni=ni, nf=nf)
+                else:
+                    D.dsr_publish_list(r, refs, D.DSR_BODY_FMA_CHAIN_REFS, n, inp=x.data_ptr(),
+                                       out=y.data_ptr(), ni=ni, nf=nf)
+                D.dsr_pop(r, f)
+                for _ in range(3):
+                    D.dsr_launch(r, stream)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                cur = torch.cuda.current_stream()
+                e0.record(cur)
+                for _ in range(reps):
+                    D.dsr_launch(r, stream)
+                e1.record(cur)
+                torch.cuda.synchronize()
+                ok = D.dsr_region_sync(r) == 0 and D.dsr_region_reduction(r, 0)[1] == want
+                lst = D.dsr_region_trace(r, 0).get("list")
+                row[mode] = {"us_per_launch": e0.elapsed_time(e1) * 1e3 / reps, "verified": bool(ok),
+                             "list_in": lst[0] if lst else None}
+                D.dsr_region_free(r)
+                D.dsr_destroy(ctx)
+            rows["K%d" % K] = row
+            say("lists", n, K, {m: round(row[m]["us_per_launch"], 2) for m in ("frame", "list", "global_list")})
+        out["n%d_teams%d" % (n, teams)] = rows
+        del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 # ---- plain region -------------------------------------------------------------
 def run_plain(torch, np, D, W, stream):
     from oracle import ref as R
@@ -307,7 +375,7 @@ def run_plain(torch, np, D, W, stream):
 def run_arrays(torch, np, D, W, stream, reps=6):
     from oracle import ref as R
     n, teams = 1 << 26, 2048
-    lds_max = 163840 - 704
+    lds_max = 163840 - D.dsr_control_bytes(WG)
     outs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(2)]
     res = {}
     for A in W.CFG3_AS:
@@ -340,7 +408,7 @@ def run_arrays(torch, np, D, W, stream, reps=6):
                 torch.cuda.synchronize()
                 ms = e0.elapsed_time(e1) / reps
                 row[mode] = {"ms": ms, "gbs": 4.0 * n / (ms * 1e-3) / 1e9,
-                             "frame_in": "lds" if slab else "hbm", "lds_bytes_per_team": 704 + slab}
+                             "frame_in": "lds" if slab else "hbm", "lds_bytes_per_team": D.dsr_control_bytes(WG) + slab}
                 if mode == "lds":
                     ok = D.dsr_region_sync(regs[(reps - 1) % 2]) == 0
                     idx = np.random.default_rng(A * 7 + length).integers(0, n, 256)
@@ -550,10 +618,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--parts", default="sweep,plain,arrays,batched,served,cpu",
-                    help="comma list of: sweep plain arrays batched served cpu calib")
+    ap.add_argument("--parts", default="sweep,plain,arrays,lists,batched,served,cpu",
+                    help="comma list of: sweep plain arrays lists batched served cpu calib")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-hbm-only", action="store_true")
+    ap.add_argument("--no-phases", action="store_true",
+                    help="skip the traced launches that measure the loop phase")
     ap.add_argument("--master-joins", type=int, default=0)
     ap.add_argument("--schedule", choices=["static", "dynamic"], default="static")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
@@ -611,6 +681,9 @@ def main():
         for k in ("per_k_kernel_ms", "per_k_gbs", "loop_phase_us", "loop_phase_gbs",
                   "team_phases_us", "lds_bytes_per_team", "hbm_only_stack", "verified"):
             out[k] = sw[k]
+    if "lists" in parts:
+        say("lists")
+        out["reference_lists"] = run_lists(torch, np, D, W, stream)
     if "calib" in parts:
         say("calib")
         out["calibration_copy"] = run_calib(torch)

@@ -89,16 +89,26 @@ extern "C" {
  *     16-byte inner frame {lo, hi, stride, outer frame} on its own LDS
  *     sub-stack and hands it to its four 16-lane groups (the inner level),
  *     then pops it (section 3.1.2 nesting; section 7 worker-level sharing).
+ *
+ * DSR_BODY_FMA_CHAIN_REFS  the DSR_BODY_FMA_CHAIN loop, published with
+ *     dsr_publish_list: no frame layout, a list of references instead
+ *     (section 5.2): reference 0 the 24-byte exact sum slot, then ni int32
+ *     scalars, nf fp64 scalars and, if alen > 0, the int32 array, each
+ *     anywhere in any live frame.
  */
 #define DSR_BODY_TERMINATE      0
 #define DSR_BODY_AFFINE_XOR     1
 #define DSR_BODY_FMA_CHAIN      2
 #define DSR_BODY_GATHER         3
 #define DSR_BODY_GATHER_NESTED  4
+#define DSR_BODY_FMA_CHAIN_REFS 5
 
 /* ---- configuration -------------------------------------------------------- */
 #define DSR_F_TRACE        1u  /* record frame placements and barrier counts   */
 #define DSR_F_TIMING       2u  /* record HIP events around every launch        */
+#define DSR_F_GLOBAL_LISTS 4u  /* every published reference list goes to the
+                                  HBM stack, however short (the global list of
+                                  section 5.2, for comparison)                */
 
 typedef struct dsr_config {
     uint32_t wg_size;            /* threads per team: multiple of 64 in [64, 1024] */
@@ -106,7 +116,8 @@ typedef struct dsr_config {
                                     goes to the HBM slab (global stack only)     */
     uint32_t overflow_threshold; /* frames larger than this go to HBM; 0 = no limit */
     uint32_t master_joins;       /* 1: the master wave also runs loop iterations
-                                    (forced when wg_size == 64)                  */
+                                    (forced when wg_size == 64; ignored above
+                                    512 threads)                                 */
     uint64_t hbm_slab_bytes;     /* HBM stack capacity per team slot              */
     uint32_t max_teams;          /* team slots in the HBM slab (allocated once by
                                     dsr_init); a launch may not exceed it        */
@@ -176,19 +187,50 @@ int dsr_push(dsr_region *r, uint32_t nbytes, const void *init, uint32_t init_byt
  * publish, numbered in publish order across the region. */
 int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr_loop *loop);
 
+/* A reference to a shared variable: `offset` bytes into live frame `frame`. */
+typedef struct dsr_ref {
+    int32_t frame;
+    uint32_t offset;
+} dsr_ref;
+
+#define DSR_LIST_ONCHIP 20     /* references the on-chip list holds (160 bytes) */
+
+/* Publish `body` (DSR_BODY_FMA_CHAIN_REFS) through a list of `n` references
+ * to the shared variables instead of a frame (section 5.1: the master hands
+ * the workers a list of references; section 5.2: the runtime keeps a
+ * 20-entry list in on-chip memory per team and falls back to a list in
+ * global memory when more are needed).  Here a list of up to
+ * DSR_LIST_ONCHIP references is written to the team's on-chip list; a
+ * longer one (or any, with DSR_F_GLOBAL_LISTS) to a list frame of 8n bytes
+ * pushed on the HBM stack at the fork and popped at the join, so a region
+ * fails with DSR_E_NOMEM when the HBM stack cannot hold it.  Workers read
+ * each reference, then the variable it names.  refs[k] must name a live
+ * frame with the variable inside it and naturally aligned (slot and fp64:
+ * 8 bytes; int32 and array: 4); n must be 1 + ni + nf + (alen > 0).
+ * Errors as dsr_publish, DSR_E_STATE for a frame that is not live. */
+int dsr_publish_list(dsr_region *r, const dsr_ref *refs, int32_t n, int32_t body, const dsr_loop *loop);
+
+/* Bytes of LDS a team of `wg_size` threads uses besides its stack slab
+ * (control block: descriptor, frame table, reference list, per-wave
+ * reduction slots and nested-level sub-stacks); 0 for a bad size. */
+uint32_t dsr_control_bytes(uint32_t wg_size);
+
 /* Pop frame `frame`; it must be the most recently pushed live frame.
  * DSR_E_UNDERFLOW on an empty stack, DSR_E_ORDER if not the top. */
 int dsr_pop(dsr_region *r, int32_t frame);
 
 /* Validate the program (DSR_E_LIVE if a frame is still live) and launch it
- * as one kernel of `teams` workgroups on `stream`.  Asynchronous: results
- * are available after dsr_region_sync.  A region may be launched again
- * (the same program over the same buffers) after its previous launch has
- * completed. */
+ * as one kernel of `teams` workgroups on `stream` (hipStream_t as void*).
+ * Asynchronous: results are available after dsr_region_sync.  A region may
+ * be launched again (the same program over the same buffers) after its
+ * previous launch, e.g. next on the same stream.  The stream must stay
+ * valid until the region is synchronised or freed. */
 int dsr_launch(dsr_region *r, void *stream);
 
 /* Wait for the region's last launch and return its device status: DSR_OK,
- * DSR_E_NOMEM (a frame fit neither stack) or DSR_E_RANGE. */
+ * DSR_E_NOMEM (a frame fit neither stack) or DSR_E_RANGE.  Without
+ * DSR_F_TIMING no event marks the launch, so this waits for everything
+ * queued on the launch stream so far. */
 int dsr_region_sync(dsr_region *r);
 
 /* Result of reducing publish `index` of the last launch (after
@@ -212,6 +254,8 @@ int dsr_region_reduction(dsr_region *r, int32_t index, int64_t *i64, double *f64
  *   [87], [88]            low words of the wall clock when the team's
  *                         program ended and when its arrival (and, for the
  *                         last team, the cross-team combine) was done
+ *   [89 .. 91]            last reference list published: where (3 on chip,
+ *                         1 HBM list frame), its offset, its entries (0: none)
  *   [96 + 2w, 97 + 2w]    low words of the wall clock when wave w started
  *                         and finished its share of the last body it ran   */
 #define DSR_TRACE_WORDS 128

@@ -26,8 +26,12 @@
  * turn it into an LDS or HBM address with frame_lds / frame_hbm.
  *
  * LDS layout of a team (dynamic shared memory):
- *   [header 64 B][frame table 16 x 16 B][per-wave reduction slots nw x 32 B]
- *   [per-wave sub-stacks nw x DSR_SUB_BYTES][stack: lds_cap bytes]
+ *   [header 64 B][frame table 16 x 16 B][reference list 20 x 8 B]
+ *   [per-wave reduction slots nw x 32 B][per-wave sub-stacks nw x DSR_SUB_BYTES]
+ *   [stack: lds_cap bytes]
+ * The reference list is the on-chip list of section 5.2: a published list
+ * of up to DSR_REF_LIST references lives there, a longer one in a list
+ * frame on the HBM stack.
  */
 #ifndef DSR_DEVICE_H
 #define DSR_DEVICE_H
@@ -39,10 +43,12 @@
 #define DSR_MAX_WAVES 16
 #define DSR_SUB_BYTES 64u
 #define DSR_ALIGN 16u
+#define DSR_REF_LIST 20u        /* references the on-chip list holds (8 B each) */
 
 namespace dsr {
 
-enum : uint32_t { SPACE_LDS = 0, SPACE_HBM = 1, SPACE_NONE = 2 };
+/* SPACE_LIST names the on-chip reference list (a published list only). */
+enum : uint32_t { SPACE_LDS = 0, SPACE_HBM = 1, SPACE_NONE = 2, SPACE_LIST = 3 };
 
 struct frame_t {
     uint32_t space;
@@ -70,7 +76,7 @@ struct cb_header {
 /* Bytes of control block for a team of nw waves. */
 __host__ __device__ constexpr uint32_t cb_bytes(uint32_t nw)
 {
-    return 64u + DSR_MAX_FRAMES * 16u + nw * 32u + nw * DSR_SUB_BYTES;
+    return 64u + DSR_MAX_FRAMES * 16u + DSR_REF_LIST * 8u + nw * 32u + nw * DSR_SUB_BYTES;
 }
 
 struct team_t {
@@ -97,13 +103,14 @@ __device__ inline void wave_sync()
 
 __device__ inline cb_header *header(const team_t &T) { return (cb_header *)T.lds; }
 __device__ inline uint32_t *frame_table(const team_t &T) { return (uint32_t *)(T.lds + 64); }
+__device__ inline uint32_t *ref_list(const team_t &T) { return (uint32_t *)(T.lds + 64 + DSR_MAX_FRAMES * 16); }
 __device__ inline uint64_t *red_slot(const team_t &T, uint32_t w)
 {
-    return (uint64_t *)(T.lds + 64 + DSR_MAX_FRAMES * 16 + w * 32);
+    return (uint64_t *)(T.lds + 64 + DSR_MAX_FRAMES * 16 + DSR_REF_LIST * 8 + w * 32);
 }
 __device__ inline uint8_t *sub_stack(const team_t &T, uint32_t w)
 {
-    return T.lds + 64 + DSR_MAX_FRAMES * 16 + T.nw * 32 + w * DSR_SUB_BYTES;
+    return T.lds + 64 + DSR_MAX_FRAMES * 16 + DSR_REF_LIST * 8 + T.nw * 32 + w * DSR_SUB_BYTES;
 }
 
 /* ~__kmpc_kernel_init.  Called by every thread of the team; the master
@@ -152,15 +159,16 @@ __device__ inline void team_reset(team_t &T)
 
 /* Master wave: place a frame of nbytes (rounded up to 16).  LDS when it
  * fits and is not above the overflow threshold, else the HBM slot, else
- * SPACE_NONE (out of memory; nothing is allocated). */
-__device__ inline frame_t push(team_t &T, uint32_t nbytes)
+ * SPACE_NONE (out of memory; nothing is allocated).  global_only keeps the
+ * frame off the LDS stack (a global reference list). */
+__device__ inline frame_t push(team_t &T, uint32_t nbytes, bool global_only = false)
 {
     cb_header *h = header(T);
     const uint32_t size = (nbytes + DSR_ALIGN - 1) & ~(DSR_ALIGN - 1);
     uint32_t spl = uniform(h->sp_lds), sph = uniform(h->sp_hbm), nf = uniform(h->nframes);
     frame_t f;
     f.size = size;
-    if (size <= T.threshold && size <= T.lds_cap - spl) {
+    if (!global_only && size <= T.threshold && size <= T.lds_cap - spl) {
         f.space = SPACE_LDS; f.off = spl; spl += size;
     } else if (size <= T.hbm_cap - sph) {
         f.space = SPACE_HBM; f.off = sph; sph += size;

@@ -46,6 +46,14 @@ Loop bodies (their frame layouts are the bodies' contracts):
                frame {lo, hi, stride, outer frame id} on its own sub-stack
                and hands it to its inner members (a second, nested parallel
                level), then pops it.
+  fma_chain_refs the fma_chain loop published through a list of references
+               (section 5.2): reference 0 is the 24-byte exact sum slot,
+               then ni int32 scalars, nf fp64 scalars and, if alen > 0, the
+               int32 array, each anywhere in a live frame.  Lists of up to
+               20 references go to the team's on-chip list (160 bytes);
+               longer ones to a list frame on the global-memory stack,
+               pushed at the fork and popped at the join.  Workers read a
+               reference, then the variable through it, on every use.
 
 Sizes are rounded up to ``align`` (16) bytes; frame offsets are multiples
 of it.  Fractions give correctly rounded fma (one rounding of the exact
@@ -59,7 +67,9 @@ import struct
 
 import numpy as np
 
-LDS, HBM = "lds", "hbm"
+LDS, HBM, CTL = "lds", "hbm", "ctl"
+REF_LIST_ENTRIES = 20             # references the on-chip list holds
+REF_BYTES = 8                     # a reference: space (u32), offset (u32)
 SLOT_F64_EXACT = 24
 UNIT_EXP = 75                     # exact sums are integers in units of 2**-75
 WINDOW_EXP = 32                   # |y| must be below 2**32
@@ -109,6 +119,13 @@ class Publish:
 
 
 @dataclass
+class PublishList:
+    refs: list                    # (push index, byte offset) per shared variable
+    body: str
+    loop: dict = field(default_factory=dict)
+
+
+@dataclass
 class Pop:
     frame: int
 
@@ -127,6 +144,7 @@ class FrameRec:
 class TeamTrace:
     placements: list = field(default_factory=list)   # (space, off, size) per push
     sub_placements: list = field(default_factory=list)
+    lists: list = field(default_factory=list)        # (space, off, entries) per list publish
     master_barriers: int = 0
     worker_barriers: list = field(default_factory=list)
     partials: list = field(default_factory=list)     # slot value after each join
@@ -180,7 +198,8 @@ class Team:
         self.tid = tid
         self.cfg = cfg
         self.n_teams = n_teams
-        self.mem = {LDS: Memory(LDS, cfg.lds_bytes), HBM: Memory(HBM, cfg.hbm_bytes)}
+        self.mem = {LDS: Memory(LDS, cfg.lds_bytes), HBM: Memory(HBM, cfg.hbm_bytes),
+                    CTL: Memory(CTL, REF_LIST_ENTRIES * REF_BYTES)}
         self.sp = {LDS: 0, HBM: 0}
         self.frames = []           # live team-level frames, bottom .. top
         self.by_id = {}
@@ -252,12 +271,12 @@ class Team:
         return hashlib.sha256(bytes(self.mem[f.space].data[f.off:f.off + f.nbytes])).hexdigest()
 
     # -- stack operations (master only) -----------------------------------
-    def push(self, fid, nbytes):
+    def push(self, fid, nbytes, global_only=False):
         if nbytes < 0:
             raise SimError("INVAL", "negative frame size")
         size = round_up(nbytes, self.cfg.align)
         c = self.cfg
-        if size <= c.threshold and self.sp[LDS] + size <= c.lds_bytes:
+        if not global_only and size <= c.threshold and self.sp[LDS] + size <= c.lds_bytes:
             space = LDS
         elif self.sp[HBM] + size <= c.hbm_bytes:
             space = HBM
@@ -267,7 +286,8 @@ class Team:
         self.sp[space] += size
         self.frames.append(f)
         self.by_id[fid] = f
-        self.trace.placements.append((space, f.off, size))
+        if not global_only:
+            self.trace.placements.append((space, f.off, size))
         m = self.mem[space]
         for b in range(f.off, f.off + size):   # a new frame holds no one's data
             m.writer[b] = None
@@ -419,8 +439,60 @@ class Gather(Body):
         return 0
 
 
+class FmaChainRefs(Body):
+    """fma_chain through references: every variable is reached by reading
+    its reference from the list, then the variable (section 5.2)."""
+    has_reduction = True
+    slot_bytes = SLOT_F64_EXACT
+
+    def iteration(self, team, lst, who, i, loop):
+        ni, nf, alen = loop["ni"], loop["nf"], loop.get("alen", 0)
+        xi = float(loop["x"][i])
+        acc = 0.0
+        if alen:
+            sp, off = lst.ref(team, 1 + ni + nf, who)
+            acc = float(_i32(team.access(sp, off + 4 * (i % alen), 4, who, False)))
+        for k in range(ni):
+            sp, off = lst.ref(team, 1 + k, who)
+            acc = fma(float(_i32(team.access(sp, off, 4, who, False))), xi, acc)
+        for k in range(nf):
+            sp, off = lst.ref(team, 1 + ni + k, who)
+            acc = fma(_f64(team.access(sp, off, 8, who, False)), xi, acc)
+        loop["y"][i] = acc
+        u = to_units(acc)
+        if u is None:
+            raise SimError("RANGE", "y[%d] = %r is outside the exact-sum window" % (i, acc))
+        return u
+
+
 BODIES = {"affine_xor": AffineXor(), "fma_chain": FmaChain(), "gather": Gather(),
-          "gather_nested": Gather()}
+          "gather_nested": Gather(), "fma_chain_refs": FmaChainRefs()}
+SPACE_CODE = {LDS: 0, HBM: 1}
+CODE_SPACE = {0: LDS, 1: HBM}
+
+
+class RefList:
+    """A published list of references: in the team's on-chip list area or
+    in a list frame on the global-memory stack."""
+
+    def __init__(self, frame):
+        self.frame = frame
+
+    def ref(self, team, k, who):
+        b = team.access(self.frame.space, self.frame.off + REF_BYTES * k, REF_BYTES, who, False,
+                        frames=[self.frame])
+        code, off = struct.unpack("<II", b)
+        if code not in CODE_SPACE:
+            raise Violation("reference %d names no space" % k)
+        return CODE_SPACE[code], off
+
+    def view(self, team, n, sizes):
+        """Bytes of the list and of every variable it references."""
+        h = hashlib.sha256(bytes(team.mem[self.frame.space].data[self.frame.off:self.frame.off + REF_BYTES * n]))
+        for k in range(n):
+            code, off = struct.unpack_from("<II", team.mem[self.frame.space].data, self.frame.off + REF_BYTES * k)
+            h.update(bytes(team.mem[CODE_SPACE[code]].data[off:off + sizes[k]]))
+        return h.hexdigest()
 
 
 # ---- the region ----------------------------------------------------------
@@ -454,6 +526,8 @@ def run_team(team, program, interleaving=None):
                 if op.frame >= len(pushed) or pushed[op.frame] not in team.frames:
                     raise SimError("STATE", "publish of a frame that is not live")
                 publish(team, pushed[op.frame], op, rng, interleaving)
+            elif isinstance(op, PublishList):
+                publish_list(team, pushed, op, rng, interleaving)
             else:
                 raise SimError("INVAL", "unknown op %r" % (op,))
         if team.frames:
@@ -499,6 +573,68 @@ def publish(team, f, op, rng, interleaving):
         team.trace.partials.append(None)
 
 
+def ref_sizes(body, loop):
+    """Bytes of each referenced variable of a list-published body."""
+    if body != "fma_chain_refs":
+        raise SimError("INVAL", "body %r takes no reference list" % body)
+    ni, nf, alen = loop["ni"], loop["nf"], loop.get("alen", 0)
+    return [SLOT_F64_EXACT] + [4] * ni + [8] * nf + ([4 * alen] if alen else [])
+
+
+def publish_list(team, pushed, op, rng, interleaving):
+    """Fork through a list of references (section 5.2): up to 20 go to the
+    team's on-chip list, more to a list frame on the global-memory stack
+    that lives from the fork to the join."""
+    cfg = team.cfg
+    sizes = ref_sizes(op.body, op.loop)
+    if len(op.refs) != len(sizes):
+        raise SimError("INVAL", "%d references for %d variables" % (len(op.refs), len(sizes)))
+    entries = []
+    for (idx, off), nb in zip(op.refs, sizes):
+        if idx >= len(pushed) or pushed[idx] not in team.frames:
+            raise SimError("STATE", "reference into a frame that is not live")
+        f = pushed[idx]
+        if off < 0 or off + nb > f.nbytes:
+            raise SimError("INVAL", "reference outside its frame")
+        entries.append(struct.pack("<II", SPACE_CODE[f.space], f.off + off))
+    n = len(entries)
+    if n <= REF_LIST_ENTRIES:
+        lf = FrameRec("list", CTL, 0, REF_LIST_ENTRIES * REF_BYTES, REF_BYTES * n, "team")
+        m = team.mem[CTL]
+        for b in range(REF_BYTES * n):
+            m.writer[b] = None
+            m.phase[b] = -1
+        team.access(CTL, 0, REF_BYTES * n, "master", True, b"".join(entries), frames=[lf])
+        global_list = None
+    else:
+        global_list = ("list", len(team.trace.lists))
+        lf = team.push(global_list, REF_BYTES * n, global_only=True)
+        team.write(lf, 0, b"".join(entries), "master")
+    team.trace.lists.append((lf.space, lf.off, n))
+    lst = RefList(lf)
+    body = BODIES[op.body]
+    loop = op.loop
+    master_view = lst.view(team, n, sizes)
+    team.barrier("all")                                   # fork: release workers
+    for w in range(cfg.workers):                          # I1 at await
+        if lst.view(team, n, sizes) != master_view:
+            raise Violation("I1: worker %d sees a list or variable different from the master's" % w)
+    lo, hi = team_range(loop, team.tid, team.n_teams)
+    partial = [0] * cfg.workers
+    queues = assign(range(lo, hi), cfg.workers, cfg.schedule, rng)
+    steps = interleaving(queues) if interleaving else interleave(queues, cfg.interleave, rng)
+    for w, i in steps:
+        partial[w] += body.iteration(team, lst, "w%d" % w, i, loop)
+    team.barrier("all")                                   # join
+    sp, off = lst.ref(team, 0, "master")
+    cur = le_to_int(team.access(sp, off, SLOT_F64_EXACT, "master", False))
+    total = cur + sum(partial)
+    team.access(sp, off, SLOT_F64_EXACT, "master", True, int_to_le(total, SLOT_F64_EXACT))
+    team.trace.partials.append(total)
+    if global_list is not None:
+        team.pop(global_list)
+
+
 def run_nested(team, outer_frame, loop, lo, hi, rng):
     """Second parallel level: the workers of the outer body are outer
     members; each pushes an inner frame on its own sub-stack, hands it to
@@ -534,7 +670,7 @@ def run_region(program, n_teams, cfg=None, interleaving=None):
     traces = []
     for t in range(n_teams):
         traces.append(run_team(Team(t, cfg, n_teams), program, interleaving))
-    pubs = [op for op in program if isinstance(op, Publish)]
+    pubs = [op for op in program if isinstance(op, (Publish, PublishList))]
     reductions = []
     if any(tr.error for tr in traces):
         return traces, None

@@ -58,7 +58,8 @@ struct dsr_region {
     uint32_t *d_trace;
     dsr_dregion *d_self;                /* this region's descriptor on the device */
     hipEvent_t ev0, ev1;
-    bool timed;                         /* ev0 was recorded by the last launch */
+    bool timed;                         /* ev0, ev1 were recorded around the last launch */
+    hipStream_t stream;                 /* stream of the last launch */
     bool launched;
     dsr_dresult h_result;
     bool have_result;
@@ -91,7 +92,7 @@ extern "C" int dsr_init(dsr_ctx **out, const dsr_config *cfg, int device)
     if (c.max_teams == 0) return DSR_E_INVAL;
     if (c.hbm_slab_bytes > 0xFFFFFFF0ull || (c.hbm_slab_bytes & 15u)) return DSR_E_INVAL;
     if (c.lds_slab_bytes & 15u) return DSR_E_INVAL;
-    if (c.flags & ~(DSR_F_TRACE | DSR_F_TIMING)) return DSR_E_INVAL;
+    if (c.flags & ~(DSR_F_TRACE | DSR_F_TIMING | DSR_F_GLOBAL_LISTS)) return DSR_E_INVAL;
     const uint32_t nw = c.wg_size / 64;
     const uint64_t lds = (uint64_t)dsr::cb_bytes(nw) + c.lds_slab_bytes;
     uint32_t lds_max = kDefaultLdsPerWg;
@@ -109,6 +110,7 @@ extern "C" int dsr_init(dsr_ctx **out, const dsr_config *cfg, int device)
     ctx->device = device;
     ctx->cfg = c;
     if (nw == 1) ctx->cfg.master_joins = 1;   /* no worker wave otherwise */
+    if (nw > 8) ctx->cfg.master_joins = 0;    /* 1024-thread teams: workers only */
     ctx->nw = nw;
     ctx->lds_bytes = (uint32_t)lds;
     ctx->threshold = c.overflow_threshold ? c.overflow_threshold : 0xFFFFFFFFu;
@@ -156,6 +158,7 @@ extern "C" int dsr_region_begin(dsr_ctx *ctx, int32_t teams, dsr_region **out)
     r->d_trace = nullptr;
     r->d_self = nullptr;
     r->ev0 = r->ev1 = nullptr;
+    r->stream = nullptr;
     r->timed = false;
     r->launched = false;
     r->have_result = false;
@@ -203,15 +206,12 @@ static int frame_depth(const dsr_region *r, int32_t frame)
     return -1;
 }
 
-extern "C" int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr_loop *loop)
+/* The loop part of a publish: schedule, coverage of [0, n) by the teams,
+ * the device descriptor.  `frames` are the handles the body reads (a
+ * dynamic tail runs blocks on any team, so none may have per-team bytes). */
+static int prepare_loop(const dsr_region *r, const dsr_loop &L, const int32_t *frames, int nframes,
+                        dsr_dloop *out)
 {
-    if (!r || !loop) return DSR_E_INVAL;
-    if (r->frozen) return DSR_E_STATE;
-    const int depth = frame_depth(r, frame);
-    if (depth < 0) return DSR_E_STATE;
-    if (r->loops.size() >= DSR_MAX_LOOPS || r->ops.size() >= DSR_MAX_OPS) return DSR_E_INVAL;
-    const dsr_loop L = *loop;
-    const uint32_t nb = r->nbytes[frame];
     if (L.n > 0x7FFFFFFFull) return DSR_E_INVAL;
     uint64_t chunk = L.chunk;
     uint64_t dyn_start = L.n;
@@ -230,7 +230,8 @@ extern "C" int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr
         if (pct > 99 || (block & 127u) || block > 65536) return DSR_E_INVAL;
         /* a block can run on any team: every team's frame must be the same */
         for (const dsr_op &o : r->ops)
-            if (o.kind == DSR_OP_PUSH && o.frame == (uint32_t)frame && o.init_stride) return DSR_E_INVAL;
+            for (int k = 0; k < nframes; ++k)
+                if (o.kind == DSR_OP_PUSH && o.frame == (uint32_t)frames[k] && o.init_stride) return DSR_E_INVAL;
         chunk = (L.n * (100 - pct) / 100) / r->teams;
         chunk &= ~63ull;
         dyn_start = chunk * (uint64_t)r->teams;
@@ -239,6 +240,44 @@ extern "C" int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr
         return DSR_E_INVAL;
     }
     if (L.n && !L.out) return DSR_E_INVAL;
+    dsr_dloop dl{};
+    dl.n = L.n;
+    dl.chunk = chunk;
+    dl.in = L.in;
+    dl.out = L.out;
+    dl.ni = L.ni;
+    dl.nf = L.nf;
+    dl.alen = L.alen;
+    dl.arrays = L.arrays;
+    dl.len = L.len;
+    dl.schedule = L.schedule;
+    dl.block = block;
+    dl.dyn_start = dyn_start;
+    *out = dl;
+    return DSR_OK;
+}
+
+/* A lane's fp64 bins stay exact for up to 2^16 values: the static share of
+ * a lane is bounded here, dynamic blocks flush the bins as they go. */
+static bool lane_share_ok(const dsr_region *r, uint64_t chunk)
+{
+    const uint64_t lanes = 64ull * (r->ctx->cfg.master_joins ? r->ctx->nw : r->ctx->nw - 1);
+    return (chunk + lanes - 1) / lanes <= (1ull << 15);
+}
+
+extern "C" int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr_loop *loop)
+{
+    if (!r || !loop) return DSR_E_INVAL;
+    if (r->frozen) return DSR_E_STATE;
+    const int depth = frame_depth(r, frame);
+    if (depth < 0) return DSR_E_STATE;
+    if (r->loops.size() >= DSR_MAX_LOOPS || r->ops.size() >= DSR_MAX_OPS) return DSR_E_INVAL;
+    const dsr_loop L = *loop;
+    const uint32_t nb = r->nbytes[frame];
+    dsr_dloop dl{};
+    int rc = prepare_loop(r, L, &frame, 1, &dl);
+    if (rc) return rc;
+    const uint64_t chunk = dl.chunk;
     bool reduces = false;
     switch (body) {
     case DSR_BODY_AFFINE_XOR:
@@ -251,12 +290,7 @@ extern "C" int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr
         uint64_t need = 24 + 8ull * L.nf + 4ull * L.ni;
         if (L.alen) need = ((need + 15) & ~15ull) + 4ull * L.alen;
         if (nb < need) return DSR_E_INVAL;
-        /* a lane's fp64 bins stay exact for up to 2^16 values; the static
-         * share is bounded here, dynamic blocks flush the bins as they go */
-        {
-            const uint64_t lanes = 64ull * (r->ctx->cfg.master_joins ? r->ctx->nw : r->ctx->nw - 1);
-            if ((chunk + lanes - 1) / lanes > (1ull << 15)) return DSR_E_INVAL;
-        }
+        if (!lane_share_ok(r, chunk)) return DSR_E_INVAL;
         if (L.alen == 0 && L.ni == 16 && L.nf == 16 && r->variant < 1) r->variant = 1;
         if (L.alen == 0 && L.ni == 32 && L.nf == 32) r->variant = 2;
         reduces = true;
@@ -272,19 +306,6 @@ extern "C" int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr
         return DSR_E_INVAL;
     }
     if (reduces && r->n_red >= DSR_MAX_RED) return DSR_E_INVAL;
-    dsr_dloop dl{};
-    dl.n = L.n;
-    dl.chunk = chunk;
-    dl.in = L.in;
-    dl.out = L.out;
-    dl.ni = L.ni;
-    dl.nf = L.nf;
-    dl.alen = L.alen;
-    dl.arrays = L.arrays;
-    dl.len = L.len;
-    dl.schedule = L.schedule;
-    dl.block = block;
-    dl.dyn_start = dyn_start;
     dsr_op op{};
     op.kind = DSR_OP_PUBLISH;
     op.frame = (uint32_t)depth;
@@ -303,6 +324,63 @@ extern "C" int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr
         return DSR_E_NOMEM;
     }
     return DSR_OK;
+}
+
+extern "C" int dsr_publish_list(dsr_region *r, const dsr_ref *refs, int32_t n, int32_t body,
+                                const dsr_loop *loop)
+{
+    if (!r || !loop || (n > 0 && !refs)) return DSR_E_INVAL;
+    if (r->frozen) return DSR_E_STATE;
+    if (body != DSR_BODY_FMA_CHAIN_REFS) return DSR_E_INVAL;
+    if (r->loops.size() >= DSR_MAX_LOOPS || r->ops.size() >= DSR_MAX_OPS) return DSR_E_INVAL;
+    const dsr_loop L = *loop;
+    if (L.ni + L.nf > 64) return DSR_E_INVAL;
+    if (n != (int32_t)(1 + L.ni + L.nf + (L.alen ? 1 : 0))) return DSR_E_INVAL;
+    if (L.n && !L.in) return DSR_E_INVAL;
+    std::vector<uint32_t> table(2 * (size_t)n);
+    std::vector<int32_t> handles(n);
+    for (int32_t k = 0; k < n; ++k) {
+        const int depth = frame_depth(r, refs[k].frame);
+        if (depth < 0) return DSR_E_STATE;
+        /* slot, int32 scalars, fp64 scalars, array */
+        const uint64_t size = k == 0 ? 24 : (k <= (int32_t)L.ni ? 4 : (k <= (int32_t)(L.ni + L.nf) ? 8 : 4ull * L.alen));
+        const uint32_t align = (k == 0 || (k > (int32_t)L.ni && k <= (int32_t)(L.ni + L.nf))) ? 8 : 4;
+        if (refs[k].offset % align || (uint64_t)refs[k].offset + size > r->nbytes[refs[k].frame]) return DSR_E_INVAL;
+        table[2 * k] = (uint32_t)depth;
+        table[2 * k + 1] = refs[k].offset;
+        handles[k] = refs[k].frame;
+    }
+    dsr_dloop dl{};
+    int rc = prepare_loop(r, L, handles.data(), n, &dl);
+    if (rc) return rc;
+    if (!lane_share_ok(r, dl.chunk)) return DSR_E_INVAL;
+    if (r->n_red >= DSR_MAX_RED) return DSR_E_INVAL;
+    dsr_op op{};
+    op.kind = DSR_OP_PUBLISH;
+    op.frame = 0xffffffffu;
+    op.body = (uint32_t)body;
+    op.loop = (uint32_t)r->loops.size();
+    op.nbytes = (uint32_t)n;
+    op.red = r->n_red;
+    try {
+        const size_t off = (r->init.size() + 15) & ~(size_t)15;
+        r->init.resize(off + table.size() * 4, 0);
+        std::memcpy(r->init.data() + off, table.data(), table.size() * 4);
+        op.init_off = off;
+        r->loops.push_back(dl);
+        r->ops.push_back(op);
+    } catch (...) {
+        return DSR_E_NOMEM;
+    }
+    r->red_kind_mask |= 1u << r->n_red;
+    r->n_red++;
+    return DSR_OK;
+}
+
+extern "C" uint32_t dsr_control_bytes(uint32_t wg_size)
+{
+    if (wg_size < 64 || wg_size > 1024 || (wg_size & 63u)) return 0;
+    return dsr::cb_bytes(wg_size / 64);
 }
 
 extern "C" int dsr_pop(dsr_region *r, int32_t frame)
@@ -384,8 +462,9 @@ static dsr_dconfig make_dconfig(const dsr_ctx *c, uint32_t wg, uint32_t lds_slab
     C.nw = wg / 64;
     C.lds_cap = lds_slab;
     C.threshold = threshold ? threshold : 0xFFFFFFFFu;
-    C.master_joins = (joins || C.nw == 1) ? 1u : 0u;
+    C.master_joins = ((joins && C.nw <= 8) || C.nw == 1) ? 1u : 0u;
     C.trace = trace;
+    C.global_lists = (c->cfg.flags & DSR_F_GLOBAL_LISTS) ? 1u : 0u;
     return C;
 }
 
@@ -408,23 +487,34 @@ extern "C" int dsr_launch(dsr_region *r, void *stream)
     LP.n_regions = 1;
     const dsr_dconfig C = make_dconfig(c, c->cfg.wg_size, c->cfg.lds_slab_bytes, c->cfg.overflow_threshold,
                                        c->cfg.master_joins, (c->cfg.flags & DSR_F_TRACE) ? 1u : 0u);
+    /* events only when timing is asked for: a marker between back-to-back
+     * launches costs about as much as a small region's fixed overhead */
     const bool timing = (c->cfg.flags & DSR_F_TIMING) != 0;
     if (timing && hipEventRecord(r->ev0, s) != hipSuccess) return DSR_E_HIP;
     if (dsr_launch_region_kernel(&LP, &C, (uint32_t)r->teams, c->cfg.wg_size, c->lds_bytes, r->variant,
                                  stream) != 0)
         return DSR_E_HIP;
-    if (hipEventRecord(r->ev1, s) != hipSuccess) return DSR_E_HIP;
+    if (timing && hipEventRecord(r->ev1, s) != hipSuccess) return DSR_E_HIP;
+    r->stream = s;
     r->timed = timing;
     r->launched = true;
     r->have_result = false;
     return DSR_OK;
 }
 
+/* Wait for a region's last launch: its end event when it was timed, else
+ * everything queued on its stream so far. */
+static int wait_launch(dsr_region *r)
+{
+    const hipError_t e = r->timed ? hipEventSynchronize(r->ev1) : hipStreamSynchronize(r->stream);
+    return e == hipSuccess ? DSR_OK : DSR_E_HIP;
+}
+
 extern "C" int dsr_region_sync(dsr_region *r)
 {
     if (!r) return DSR_E_INVAL;
     if (!r->launched) return DSR_E_STATE;
-    if (hipEventSynchronize(r->ev1) != hipSuccess) return DSR_E_HIP;
+    if (wait_launch(r)) return DSR_E_HIP;
     if (hipMemcpy(&r->h_result, r->d_result, sizeof(dsr_dresult), hipMemcpyDeviceToHost) != hipSuccess)
         return DSR_E_HIP;
     r->have_result = true;
@@ -449,7 +539,7 @@ extern "C" int dsr_region_trace(dsr_region *r, int32_t team, uint32_t *buf, uint
     if (!r->d_trace) return DSR_E_STATE;
     if (team < 0 || team >= r->teams) return DSR_E_INVAL;
     if (!r->launched) return DSR_E_STATE;
-    if (hipEventSynchronize(r->ev1) != hipSuccess) return DSR_E_HIP;
+    if (wait_launch(r)) return DSR_E_HIP;
     if (hipMemcpy(buf, r->d_trace + (size_t)team * DSR_TRACE_WORDS, DSR_TRACE_WORDS * sizeof(uint32_t),
                   hipMemcpyDeviceToHost) != hipSuccess)
         return DSR_E_HIP;
@@ -467,7 +557,7 @@ extern "C" int dsr_region_elapsed(dsr_region *r, float *ms)
 extern "C" int dsr_region_free(dsr_region *r)
 {
     if (!r) return DSR_E_INVAL;
-    if (r->launched) hipEventSynchronize(r->ev1);
+    if (r->launched) (void)wait_launch(r);
     if (r->d_ops) hipFree(r->d_ops);
     if (r->d_loops) hipFree(r->d_loops);
     if (r->d_init) hipFree(r->d_init);
@@ -664,6 +754,7 @@ extern "C" int dsr_batch_tune(dsr_batch *b, const dsr_tune *tune)
     const uint64_t lds = (uint64_t)dsr::cb_bytes(nw) + t.lds_slab_bytes;
     if (lds > b->lds_max) return DSR_E_LDS;
     if (nw == 1) t.master_joins = 1;
+    if (nw > 8) t.master_joins = 0;
     /* the static share of a lane must stay within the exact bins' range */
     const uint64_t lanes = 64ull * (t.master_joins ? nw : nw - 1);
     for (int32_t i = 0; i < b->n; ++i)
@@ -909,6 +1000,12 @@ bool stack_peaks(const dsr_region *r, uint32_t lds_cap, uint32_t threshold, uint
         } else if (op.kind == DSR_OP_POP && !live.empty()) {
             if (live.back().first == 0) spl -= live.back().second; else sph -= live.back().second;
             live.pop_back();
+        } else if (op.kind == DSR_OP_PUBLISH && op.body == DSR_BODY_FMA_CHAIN_REFS &&
+                   (op.nbytes > DSR_LIST_ONCHIP || (r->ctx->cfg.flags & DSR_F_GLOBAL_LISTS))) {
+            /* a global reference list lives on the HBM stack for the region */
+            const uint64_t size = (8ull * op.nbytes + 15) & ~15ull;
+            if (sph + size > hbm_cap) return false;
+            *hbm_peak = std::max(*hbm_peak, sph + size);
         }
     }
     return true;
@@ -957,6 +1054,7 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
     if (t.wg_size < 64 || t.wg_size > 1024 || (t.wg_size & 63u) || (t.lds_slab_bytes & 15u)) return DSR_E_INVAL;
     const uint32_t nw = t.wg_size / 64;
     if (nw == 1) t.master_joins = 1;
+    if (nw > 8) t.master_joins = 0;
     int v = 0;
     uint32_t lds_max = kDefaultLdsPerWg, cus = 1;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) == hipSuccess && v > 0)

@@ -123,6 +123,8 @@ struct dsr_dconfig {
     uint32_t master_joins;
     uint32_t trace;
     uint32_t serve;        /* served form: per-item program copy after the stack */
+    uint32_t global_lists; /* every reference list goes to the HBM stack      */
+    uint32_t pad;
 };
 
 #ifdef __cplusplus

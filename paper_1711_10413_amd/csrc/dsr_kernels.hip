@@ -36,6 +36,12 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
+/* Element pairs per lane and batch in the run-time fma chain (256- and
+ * 512-thread instances). */
+#ifndef DSR_RT_PAIRS
+#define DSR_RT_PAIRS 8
+#endif
+
 extern __shared__ __align__(16) uint8_t dsr_lds[];
 
 /* Address-space qualifiers: loop buffers are global memory; without the
@@ -367,6 +373,15 @@ __device__ __forceinline__ double uniform_f64(const uint8_t *p)
 }
 
 template <int NI, int NF>
+__device__ __forceinline__ void fma_fixed_spans(const double (&s)[NI + NF], const dsr_dloop &L, span_t sp,
+                                                lane_acc &A, uint32_t *claim, uint32_t lane)
+{
+    const GLB float *x = (const GLB float *)L.in;
+    GLB double *y = (GLB double *)L.out;
+    for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_span<NI, NF>(s, x, y, q, A); });
+}
+
+template <int NI, int NF>
 __device__ __forceinline__ void body_fma_fixed(const uint8_t *fb, const dsr_dloop &L, span_t sp,
                                                lane_acc &A, uint32_t *claim, uint32_t lane)
 {
@@ -375,18 +390,28 @@ __device__ __forceinline__ void body_fma_fixed(const uint8_t *fb, const dsr_dloo
     for (int k = 0; k < NI; ++k) s[k] = (double)(int32_t)uniform_u32(fb + 24 + 8 * NF + 4 * k);
 #pragma unroll
     for (int k = 0; k < NF; ++k) s[NI + k] = uniform_f64(fb + 24 + 8 * k);
-    const GLB float *x = (const GLB float *)L.in;
-    GLB double *y = (GLB double *)L.out;
-    for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_span<NI, NF>(s, x, y, q, A); });
+    fma_fixed_spans<NI, NF>(s, L, sp, A, claim, lane);
 }
 
-/* fma chain with a run-time scalar count n <= 64 and an optional shared
- * int32 array (the chain then starts from the array element).  Lane k of
- * the wave holds scalar k as a double (`sv`); each step of the chain takes
- * it with two readlanes into scalar registers, shared by all the elements
- * of a batch.  The array index i mod alen is carried from element to
- * element (one conditional subtraction per step) instead of divided.  The
- * element layout, batching and software pipelining are those of fma_span. */
+/* The same chain with its scalars held one per lane (lane k: scalar k). */
+template <int NI, int NF>
+__device__ __forceinline__ void lanes_fma_fixed(double sv, const dsr_dloop &L, span_t sp, lane_acc &A,
+                                                uint32_t *claim, uint32_t lane);
+
+/* fma chain with a run-time scalar count (at most 64) and an optional
+ * shared int32 array (the chain then starts from the array element).  The
+ * scalars come from one of two sources:
+ *   lds_scalars   the frame is in LDS: each chain step reads its scalar with
+ *                 a wave-uniform LDS load (a broadcast) shared by every
+ *                 element of the batch; int32 scalars are read in pairs.
+ *   lane_scalars  the frame is in HBM: lane k holds scalar k as a double
+ *                 (loaded once per body) and each step takes it with two
+ *                 readlanes.
+ * The array index i mod alen is carried from element to element (one
+ * conditional subtraction per step) instead of divided.  The element
+ * layout, batching and software pipelining are those of fma_span. */
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ double readlane_f64(double v, uint32_t k)
 {
     const uint64_t b = (uint64_t)__double_as_longlong(v);
@@ -395,40 +420,80 @@ __device__ __forceinline__ double readlane_f64(double v, uint32_t k)
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+template <int NI, int NF>
+__device__ __forceinline__ void lanes_fma_fixed(double sv, const dsr_dloop &L, span_t sp, lane_acc &A,
+                                                uint32_t *claim, uint32_t lane)
+{
+    double s[NI + NF];
+#pragma unroll
+    for (int k = 0; k < NI + NF; ++k) s[k] = readlane_f64(sv, k);
+    fma_fixed_spans<NI, NF>(s, L, sp, A, claim, lane);
+}
+
 __device__ __forceinline__ uint32_t mod_step(uint32_t j, uint32_t d, uint32_t m)
 {
     j += d;
     return j >= m ? j - m : j;
 }
 
-template <int U, class AP>
-__device__ __forceinline__ void rt_chain(double sv, uint32_t n, double (&acc)[2 * U], const double (&xd)[2 * U])
+template <int E>
+__device__ __forceinline__ void fma_all(double s, double (&acc)[E], const double (&xd)[E])
 {
-    for (uint32_t k = 0; k < n; ++k) {
-        const double sk = readlane_f64(sv, k);
 #pragma unroll
-        for (int e = 0; e < 2 * U; ++e) acc[e] = __builtin_fma(sk, xd[e], acc[e]);
+    for (int e = 0; e < E; ++e) acc[e] = __builtin_fma(s, xd[e], acc[e]);
+}
+
+struct lds_scalars {
+    const LDSQ int32_t *si;   /* ni int32 scalars (8-byte aligned) */
+    const LDSQ double *sf;    /* nf fp64 scalars                   */
+    uint32_t ni, nf;
+
+    template <int E>
+    __device__ __forceinline__ void chain(double (&acc)[E], const double (&xd)[E]) const
+    {
+        uint32_t k = 0;
+#pragma unroll 2
+        for (; k + 2 <= ni; k += 2) {
+            const i32x2 q = *(const LDSQ i32x2 *)(si + k);
+            fma_all<E>((double)q.x, acc, xd);
+            fma_all<E>((double)q.y, acc, xd);
+        }
+        if (k < ni) fma_all<E>((double)si[k], acc, xd);
+#pragma unroll 4
+        for (uint32_t f = 0; f < nf; ++f) fma_all<E>(sf[f], acc, xd);
     }
-}
+};
 
-template <bool ARR, class AP>
-__device__ __forceinline__ double rt_one(double sv, uint32_t n, AP arr, uint32_t alen, double xd, uint64_t i)
+struct lane_scalars {
+    double sv;                /* lane k: scalar k */
+    uint32_t n;
+
+    template <int E>
+    __device__ __forceinline__ void chain(double (&acc)[E], const double (&xd)[E]) const
+    {
+        for (uint32_t k = 0; k < n; ++k) fma_all<E>(readlane_f64(sv, k), acc, xd);
+    }
+};
+
+template <bool ARR, class AP, class SC>
+__device__ __forceinline__ double rt_one(const SC &sc, AP arr, uint32_t alen, double xd, uint64_t i)
 {
-    double acc = 0.0;
-    if constexpr (ARR) acc = (double)arr[(uint32_t)(i % alen)];
-    for (uint32_t k = 0; k < n; ++k) acc = __builtin_fma(readlane_f64(sv, k), xd, acc);
-    return acc;
+    double acc[1] = {0.0};
+    const double x1[1] = {xd};
+    if constexpr (ARR) acc[0] = (double)arr[(uint32_t)(i % alen)];
+    sc.template chain<1>(acc, x1);
+    return acc[0];
 }
 
-template <int U, bool ARR, class AP>
-__device__ __forceinline__ void fma_rt_span(double sv, uint32_t n, AP arr, uint32_t alen,
+template <int U, bool ARR, class AP, class SC>
+__device__ __forceinline__ void fma_rt_span(const SC &sc, AP arr, uint32_t alen,
                                             const GLB float *__restrict__ x, GLB double *__restrict__ y,
                                             span_t sp, lane_acc &A)
 {
     const uint64_t plo = min(sp.hi, (sp.lo + 1) & ~1ull);
     const uint64_t phi = max(plo, sp.hi & ~1ull);
     if (sp.lo < plo && sp.p == 0) {
-        const double v = rt_one<ARR>(sv, n, arr, alen, (double)x[sp.lo], sp.lo);
+        const double v = rt_one<ARR>(sc, arr, alen, (double)x[sp.lo], sp.lo);
         y[sp.lo] = v;
         acc_add_f64(A, v);
     }
@@ -482,7 +547,7 @@ __device__ __forceinline__ void fma_rt_span(double sv, uint32_t n, AP arr, uint3
                 acc[2 * u] = ARR ? (double)ca[2 * u] : 0.0;
                 acc[2 * u + 1] = ARR ? (double)ca[2 * u + 1] : 0.0;
             }
-            rt_chain<U, AP>(sv, n, acc, xd);
+            sc.template chain<2 * U>(acc, xd);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 f64x2 r;
@@ -507,14 +572,14 @@ __device__ __forceinline__ void fma_rt_span(double sv, uint32_t n, AP arr, uint3
     for (; v < nv1; v += sp.P) {
         const f32x2 xv = __builtin_nontemporal_load(&x2[v]);
         f64x2 r;
-        r.x = rt_one<ARR>(sv, n, arr, alen, (double)xv.x, 2 * v);
-        r.y = rt_one<ARR>(sv, n, arr, alen, (double)xv.y, 2 * v + 1);
+        r.x = rt_one<ARR>(sc, arr, alen, (double)xv.x, 2 * v);
+        r.y = rt_one<ARR>(sc, arr, alen, (double)xv.y, 2 * v + 1);
         __builtin_nontemporal_store(r, &y2[v]);
         acc_add_f64(Ac[0], r.x);
         acc_add_f64(Ac[1], r.y);
     }
     if (phi < sp.hi && sp.p == 0) {
-        const double r = rt_one<ARR>(sv, n, arr, alen, (double)x[phi], phi);
+        const double r = rt_one<ARR>(sc, arr, alen, (double)x[phi], phi);
         y[phi] = r;
         acc_add_f64(A, r);
     }
@@ -522,23 +587,39 @@ __device__ __forceinline__ void fma_rt_span(double sv, uint32_t n, AP arr, uint3
     acc_merge(A, Ac[1]);
 }
 
-/* Body entry for the run-time chain: every lane loads its scalar (lane k
- * < ni: int32 scalar k; ni <= k < ni + nf: fp64 scalar k - ni) once, then
- * the loop streams, U element pairs per lane and batch. */
-template <int U, class AP>
-__device__ __forceinline__ void body_fma_rt(const uint8_t *fb, AP arr, const dsr_dloop &L, span_t sp,
-                                            lane_acc &A, uint32_t *claim, uint32_t lane)
+template <int U, class AP, class SC>
+__device__ __forceinline__ void rt_spans(const SC &sc, AP arr, const dsr_dloop &L, uint32_t alen, span_t sp,
+                                         lane_acc &A, uint32_t *claim, uint32_t lane)
 {
-    const uint32_t ni = L.ni, nf = L.nf, alen = L.alen;
-    double sv = 0.0;
-    if (lane < ni) sv = (double)*(const int32_t *)(fb + 24 + 8 * nf + 4 * lane);
-    else if (lane < ni + nf) sv = *(const double *)(fb + 24 + 8 * (lane - ni));
     const GLB float *x = (const GLB float *)L.in;
     GLB double *y = (GLB double *)L.out;
     if (alen)
-        for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_rt_span<U, true>(sv, ni + nf, arr, alen, x, y, q, A); });
+        for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_rt_span<U, true>(sc, arr, alen, x, y, q, A); });
     else
-        for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_rt_span<U, false>(sv, ni + nf, arr, alen, x, y, q, A); });
+        for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_rt_span<U, false>(sc, arr, alen, x, y, q, A); });
+}
+
+/* Body entry for the run-time chain, frame in LDS (offset `off` in the
+ * dynamic LDS) or in HBM (`fb`); the array follows the scalars at the next
+ * 16-byte boundary.  U element pairs per lane and batch. */
+template <int U>
+__device__ __forceinline__ void body_fma_rt(const team_t &T, frame_t f, const dsr_dloop &L, span_t sp,
+                                            lane_acc &A, uint32_t *claim, uint32_t lane)
+{
+    const uint32_t ni = uniform(L.ni), nf = uniform(L.nf), alen = uniform(L.alen);
+    const uint32_t aoff = (24 + 8 * nf + 4 * ni + 15) & ~15u;
+    if (f.space == SPACE_LDS) {
+        const LDSQ uint8_t *fb = (const LDSQ uint8_t *)(dsr_lds + cb_bytes(T.nw) + f.off);
+        const lds_scalars sc{(const LDSQ int32_t *)(fb + 24 + 8 * nf), (const LDSQ double *)(fb + 24), ni, nf};
+        rt_spans<U>(sc, (const LDSQ int32_t *)(fb + aoff), L, alen, sp, A, claim, lane);
+    } else {
+        const GLB uint8_t *fb = (const GLB uint8_t *)frame_hbm(T, f);
+        double sv = 0.0;
+        if (lane < ni) sv = (double)*(const GLB int32_t *)(fb + 24 + 8 * nf + 4 * lane);
+        else if (lane < ni + nf) sv = *(const GLB double *)(fb + 24 + 8 * (lane - ni));
+        const lane_scalars sc{sv, ni + nf};
+        rt_spans<U>(sc, (const GLB int32_t *)(fb + aoff), L, alen, sp, A, claim, lane);
+    }
 }
 
 /* Shared-array gather; arrays at `arr` (LDS or global pointer), `len`
@@ -703,12 +784,40 @@ __device__ __forceinline__ void run_body(team_t &T, uint32_t body, frame_t f, co
         }
         /* run-time chain (the host admits at most 64 scalars); workgroups
          * above 512 threads have 128 registers per lane */
-        const uint32_t aoff = (24 + 8 * nf + 4 * ni + 15) & ~15u;
-        constexpr int U = VARIANT < 0 ? 1 : 4;
-        if (f.space == SPACE_LDS)
-            body_fma_rt<U>(fb, (const LDSQ int32_t *)(dsr_lds + cb_bytes(T.nw) + f.off + aoff), L, sp, A, claim, lane);
-        else
-            body_fma_rt<U>(fb, (const GLB int32_t *)(frame_hbm(T, f) + aoff), L, sp, A, claim, lane);
+        body_fma_rt<VARIANT < 0 ? 1 : DSR_RT_PAIRS>(T, f, L, sp, A, claim, lane);
+        break;
+    }
+    case DSR_BODY_FMA_CHAIN_REFS: {
+        /* the wrapper of section 5.1 over a list of references: lane j
+         * reads reference 1 + j (scalar j), then the scalar through it; the
+         * array's reference is read by every lane */
+        const uint32_t ni = uniform(L.ni), nf = uniform(L.nf), alen = uniform(L.alen);
+        const uint32_t *lst = f.space == SPACE_LIST ? ref_list(T) : (const uint32_t *)frame_hbm(T, f);
+        double sv = 0.0;
+        if (lane < ni + nf) {
+            const uint32_t sp_ = lst[2 * (1 + lane)], off = lst[2 * (1 + lane) + 1];
+            const uint8_t *p = sp_ == SPACE_LDS ? T.stack_lds + off : T.stack_hbm + off;
+            sv = lane < ni ? (double)*(const int32_t *)p : *(const double *)p;
+        }
+        /* with the counts of a compiled fixed chain, run that chain */
+        if (VARIANT >= 0 && alen == 0) {
+            if (ni == 1 && nf == 0) { lanes_fma_fixed<1, 0>(sv, L, sp, A, claim, lane); break; }
+            if (ni == 1 && nf == 1) { lanes_fma_fixed<1, 1>(sv, L, sp, A, claim, lane); break; }
+            if (ni == 2 && nf == 2) { lanes_fma_fixed<2, 2>(sv, L, sp, A, claim, lane); break; }
+            if (ni == 4 && nf == 4) { lanes_fma_fixed<4, 4>(sv, L, sp, A, claim, lane); break; }
+            if (ni == 8 && nf == 8) { lanes_fma_fixed<8, 8>(sv, L, sp, A, claim, lane); break; }
+        }
+        const lane_scalars sc{sv, ni + nf};
+        constexpr int U = VARIANT < 0 ? 1 : DSR_RT_PAIRS;
+        if (alen) {
+            const uint32_t asp = uniform(lst[2 * (1 + ni + nf)]), aoff = uniform(lst[2 * (1 + ni + nf) + 1]);
+            if (asp == SPACE_LDS)
+                rt_spans<U>(sc, (const LDSQ int32_t *)(dsr_lds + cb_bytes(T.nw) + aoff), L, alen, sp, A, claim, lane);
+            else
+                rt_spans<U>(sc, (const GLB int32_t *)(T.stack_hbm + aoff), L, alen, sp, A, claim, lane);
+        } else {
+            rt_spans<U>(sc, (const GLB int32_t *)nullptr, L, 0, sp, A, claim, lane);
+        }
         break;
     }
     case DSR_BODY_GATHER: {
@@ -890,11 +999,40 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
             init_frame(T, f, R.init + op.init_off + (uint64_t)team * op.init_stride, op.init_bytes,
                        op.nbytes);
         } else if (op.kind == DSR_OP_PUBLISH) {
-            const uint32_t *ft = frame_table(T) + 4 * op.frame;
-            frame_t f;
-            f.space = uniform(ft[0]);
-            f.off = uniform(ft[1]);
-            f.size = uniform(ft[2]);
+            frame_t f, lf{SPACE_NONE, 0, 0};
+            if (op.body == DSR_BODY_FMA_CHAIN_REFS) {
+                /* section 5.2: resolve each (frame, offset) reference to a
+                 * stack address and write the list on chip, or to a list
+                 * frame on the HBM stack when it is longer than the on-chip
+                 * list (or global lists are asked for) */
+                const uint32_t n = op.nbytes;
+                const uint32_t *tab = (const uint32_t *)(R.init + op.init_off);
+                const bool glist = n > DSR_REF_LIST || C.global_lists;
+                uint32_t *dst = ref_list(T);
+                if (glist) {
+                    lf = push(T, 8 * n, true);
+                    if (lf.space == SPACE_NONE) { err = DSR_E_NOMEM; break; }
+                    dst = (uint32_t *)frame_hbm(T, lf);
+                    f = frame_t{SPACE_HBM, lf.off, n};
+                } else {
+                    f = frame_t{SPACE_LIST, 0, n};
+                }
+                for (uint32_t k = T.lane; k < n; k += 64) {
+                    const uint32_t *fte = frame_table(T) + 4 * tab[2 * k];
+                    dst[2 * k] = fte[0];
+                    dst[2 * k + 1] = fte[1] + tab[2 * k + 1];
+                }
+                if (tr && T.lane == 0) {
+                    tr[89] = glist ? SPACE_HBM : SPACE_LIST;
+                    tr[90] = f.off;
+                    tr[91] = n;
+                }
+            } else {
+                const uint32_t *ft = frame_table(T) + 4 * op.frame;
+                f.space = uniform(ft[0]);
+                f.off = uniform(ft[1]);
+                f.size = uniform(ft[2]);
+            }
             if (T.lane == 0) {
                 h->region = region;
                 h->team = team;
@@ -907,7 +1045,9 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
                 tr[83] = (uint32_t)(t0 >> 32);
             }
             stamped = true;
-            if (C.master_joins) {
+            /* the 1024-thread instance has no registers for a participating
+             * master; the host never asks it to (teams above 512 threads) */
+            if (VARIANT >= 0 && C.master_joins) {
                 participate<VARIANT>(T, R, C, team, op.body, f, op.loop, inner_pushes);
             } else {
                 end_parallel(T, 0, 0, 0, 0);
@@ -930,31 +1070,42 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
             wave_sync();
             if (T.lane == 0) h->bad = 0;
             if (op.red != 0xffffffffu) {
-                uint8_t *fb = (uint8_t *)frame_ptr(T, f);
-                i192 slot;
+                /* the shared sum: the frame's first bytes, or where reference
+                 * 0 of the list points */
+                uint8_t *fb;
+                if (op.body == DSR_BODY_FMA_CHAIN_REFS) {
+                    const uint32_t *lst = f.space == SPACE_LIST ? ref_list(T) : (const uint32_t *)frame_hbm(T, f);
+                    const uint32_t s_space = uniform(lst[0]), s_off = uniform(lst[1]);
+                    fb = s_space == SPACE_LDS ? T.stack_lds + s_off : T.stack_hbm + s_off;
+                } else {
+                    fb = (uint8_t *)frame_ptr(T, f);
+                }
+                i192 sv;
                 if (op.body == DSR_BODY_AFFINE_XOR) {
                     const int64_t cur = *(const int64_t *)fb;
                     const int64_t nv = (int64_t)((uint64_t)cur + tot.w0);
-                    slot = i192{(uint64_t)nv, (uint64_t)(nv >> 63), (uint64_t)(nv >> 63)};
+                    sv = i192{(uint64_t)nv, (uint64_t)(nv >> 63), (uint64_t)(nv >> 63)};
                     wave_sync();
                     if (T.lane == 0) *(int64_t *)fb = nv;
                 } else {
                     const uint64_t *c = (const uint64_t *)fb;
-                    slot = add192(tot, i192{c[0], c[1], c[2]});
+                    sv = add192(tot, i192{c[0], c[1], c[2]});
                     wave_sync();
                     if (T.lane == 0) {
                         uint64_t *cw = (uint64_t *)fb;
-                        cw[0] = slot.w0; cw[1] = slot.w1; cw[2] = slot.w2;
+                        cw[0] = sv.w0; cw[1] = sv.w1; cw[2] = sv.w2;
                     }
                 }
                 if (T.lane == 0) {
                     uint64_t *pp = R.partials + ((uint64_t)op.red * R.teams + team) * 3;
-                    store_dev(pp, slot.w0);
-                    store_dev(pp + 1, slot.w1);
-                    store_dev(pp + 2, slot.w2);
+                    store_dev(pp, sv.w0);
+                    store_dev(pp + 1, sv.w1);
+                    store_dev(pp + 2, sv.w2);
                 }
             }
             wave_sync();
+            /* a global reference list dies with its parallel region */
+            if (lf.space == SPACE_HBM && !pop(T, lf)) err = DSR_E_ORDER;
             if (err) break;
         } else if (op.kind == DSR_OP_POP) {
             const uint32_t nf = uniform(h->nframes);
@@ -977,15 +1128,15 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
 }
 
 /* Sum `cnt` 192-bit partials (three words each, `stride` partials apart)
- * with the whole wave: each lane issues up to four independent loads per
- * round, so a group of up to 256 partials costs one memory round trip. */
+ * with the whole wave: each lane issues up to eight independent loads per
+ * round, so up to 512 partials cost one memory round trip. */
 __device__ __forceinline__ i192 sum_partials(const uint64_t *base, uint32_t cnt, uint32_t stride, uint32_t lane)
 {
     i192 s{0, 0, 0};
-    for (uint32_t j0 = 0; j0 < cnt; j0 += 256) {
-        uint64_t w[4][3];
+    for (uint32_t j0 = 0; j0 < cnt; j0 += 512) {
+        uint64_t w[8][3];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             const uint32_t j = j0 + 64u * u + lane;
             const uint64_t *pp = base + 3ull * j * stride;
             const bool in = j < cnt;
@@ -994,7 +1145,7 @@ __device__ __forceinline__ i192 sum_partials(const uint64_t *base, uint32_t cnt,
             w[u][2] = in ? load_dev(pp + 2) : 0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) s = add192(s, i192{w[u][0], w[u][1], w[u][2]});
+        for (int u = 0; u < 8; ++u) s = add192(s, i192{w[u][0], w[u][1], w[u][2]});
     }
     return wave_sum192(s);
 }
@@ -1036,9 +1187,10 @@ __device__ __forceinline__ void publish_record(const dsr_dregion &R, dsr_drec *r
 
 /* A team's arrival after its program.  Arrivals go through a two-level
  * tree (groups of teams, then groups) so that no counter sees more than a
- * few dozen simultaneous atomics; the last team of a group adds up the
- * group's partials and leaves the sum in the group's first partial slot,
- * and the last group's leader combines the group sums into the result. */
+ * few dozen simultaneous atomics.  With up to 512 teams the last team
+ * reads every partial in one round; with more, the last team of each group
+ * first adds up its group's partials and leaves the sum in the group's
+ * first partial slot, and the last team overall adds the group sums. */
 __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team, uint32_t lane,
                                             uint64_t *done_ts, dsr_drec *rec = nullptr)
 {
@@ -1046,6 +1198,7 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team,
     const uint32_t ngroups = (R.teams + gsize - 1) / gsize;
     const uint32_t g = team / gsize;
     const uint32_t in_group = min(gsize, R.teams - g * gsize);
+    const bool group_sums = R.teams > 512;
     drain_memory();                      /* this team's partials are stored */
     uint32_t prev = 0;
     if (lane == 0)
@@ -1054,16 +1207,18 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team,
     if (prev != in_group - 1) return;
     if (lane == 0) __hip_atomic_store(&R.result->group[g * 16], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (ngroups > 1) {
-        for (uint32_t r = 0; r < R.n_red; ++r) {
-            uint64_t *gp = R.partials + ((uint64_t)r * R.teams + (uint64_t)g * gsize) * 3;
-            const i192 s = sum_partials(gp, in_group, 1, lane);
-            if (lane == 0) {
-                store_dev(gp, s.w0);
-                store_dev(gp + 1, s.w1);
-                store_dev(gp + 2, s.w2);
+        if (group_sums) {
+            for (uint32_t r = 0; r < R.n_red; ++r) {
+                uint64_t *gp = R.partials + ((uint64_t)r * R.teams + (uint64_t)g * gsize) * 3;
+                const i192 s = sum_partials(gp, in_group, 1, lane);
+                if (lane == 0) {
+                    store_dev(gp, s.w0);
+                    store_dev(gp + 1, s.w1);
+                    store_dev(gp + 2, s.w2);
+                }
             }
+            drain_memory();              /* the group sums are stored */
         }
-        drain_memory();                  /* the group sums are stored */
         if (lane == 0)
             prev = __hip_atomic_fetch_add(&R.result->arrived, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         prev = uniform((uint32_t)__shfl((int)prev, 0, 64));
@@ -1072,7 +1227,7 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team,
     }
     int32_t err = 0;
     if (lane == 0) err = __hip_atomic_exchange(&R.result->error, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (ngroups > 1) combine_teams(R, ngroups, gsize, lane);
+    if (ngroups > 1 && group_sums) combine_teams(R, ngroups, gsize, lane);
     else combine_teams(R, R.teams, 1, lane);
     if (lane < DSR_MAX_LOOPS)
         __hip_atomic_store(&R.result->claim[lane], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

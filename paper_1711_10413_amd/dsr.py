@@ -35,12 +35,15 @@ DSR_BODY_AFFINE_XOR = 1
 DSR_BODY_FMA_CHAIN = 2
 DSR_BODY_GATHER = 3
 DSR_BODY_GATHER_NESTED = 4
+DSR_BODY_FMA_CHAIN_REFS = 5
+DSR_LIST_ONCHIP = 20
 
 DSR_SCHED_STATIC = 0
 DSR_SCHED_DYNAMIC_TAIL = 1
 
 DSR_F_TRACE = 1
 DSR_F_TIMING = 2
+DSR_F_GLOBAL_LISTS = 4
 DSR_TRACE_WORDS = 128
 
 # the exported C entry points (include/dsr.h)
@@ -51,7 +54,12 @@ EXPORTS = ("dsr_init", "dsr_destroy", "dsr_region_begin", "dsr_push", "dsr_publi
            "dsr_batch_launch_each", "dsr_batch_sync", "dsr_batch_result", "dsr_batch_times",
            "dsr_batch_elapsed", "dsr_batch_free", "dsr_autotune", "dsr_batch_replay_serial",
            "dsr_serve_start", "dsr_serve_submit", "dsr_serve_poll", "dsr_serve_pending",
-           "dsr_serve_replay", "dsr_serve_stop", "dsr_occupancy_model", "dsr_region_occupancy")
+           "dsr_serve_replay", "dsr_serve_stop", "dsr_occupancy_model", "dsr_region_occupancy",
+           "dsr_publish_list", "dsr_control_bytes")
+
+
+class dsr_ref(C.Structure):
+    _fields_ = [("frame", C.c_int32), ("offset", C.c_uint32)]
 
 
 class dsr_config(C.Structure):
@@ -149,6 +157,7 @@ def lib():
             "dsr_region_begin": [P, i32, C.POINTER(P)],
             "dsr_push": [P, u32, P, u32, u32, C.POINTER(i32)],
             "dsr_publish": [P, i32, i32, C.POINTER(dsr_loop)],
+            "dsr_publish_list": [P, C.POINTER(dsr_ref), i32, i32, C.POINTER(dsr_loop)],
             "dsr_pop": [P, i32],
             "dsr_launch": [P, P],
             "dsr_region_sync": [P],
@@ -190,6 +199,8 @@ def lib():
             f.restype = C.c_int
         L.dsr_strerror.argtypes = [C.c_int]
         L.dsr_strerror.restype = C.c_char_p
+        L.dsr_control_bytes.argtypes = [u32]
+        L.dsr_control_bytes.restype = u32
         _lib = L
     return _lib
 
@@ -244,6 +255,19 @@ def dsr_publish(region, frame, body, n, inp=0, out=0, chunk=0, ni=0, nf=0, alen=
     return _check(lib().dsr_publish(region, frame, body, C.byref(L)), "dsr_publish")
 
 
+def dsr_publish_list(region, refs, body, n, inp=0, out=0, chunk=0, ni=0, nf=0, alen=0,
+                     schedule=0, tail_pct=0, block=0):
+    """refs: (frame, byte offset) per variable: the exact sum slot, the ni
+    int32 scalars, the nf fp64 scalars, then the array if alen > 0."""
+    arr = (dsr_ref * max(1, len(refs)))(*[dsr_ref(int(f), int(o)) for f, o in refs])
+    L = dsr_loop(n, chunk, inp or None, out or None, ni, nf, alen, 0, 0, schedule, tail_pct, block)
+    return _check(lib().dsr_publish_list(region, arr, len(refs), body, C.byref(L)), "dsr_publish_list")
+
+
+def dsr_control_bytes(wg_size):
+    return lib().dsr_control_bytes(wg_size)
+
+
 def dsr_pop(region, frame):
     return _check(lib().dsr_pop(region, frame), "dsr_pop")
 
@@ -283,7 +307,9 @@ def dsr_region_trace(region, team):
             "barriers": t[49:65], "inner_pushes": t[65:81],
             "error": C.c_int32(t[81]).value,
             "t_start": t[82] | (t[83] << 32), "t_end": t[84] | (t[85] << 32),
-            "t_team": t[86], "t_program_end": t[87], "t_arrived": t[88], "wave_loop": [(t[96 + 2 * w], t[97 + 2 * w]) for w in range(16)]}
+            "t_team": t[86], "t_program_end": t[87], "t_arrived": t[88],
+            "list": (("lds", "hbm", "none", "onchip")[t[89]], t[90], t[91]) if t[91] else None,
+            "wave_loop": [(t[96 + 2 * w], t[97 + 2 * w]) for w in range(16)]}
 
 
 def dsr_region_elapsed(region):

@@ -19,7 +19,7 @@ def declared_symbols():
         if not h.endswith(".h") or h == "dsr_device.h":
             continue
         text = open(os.path.join(ROOT, "include", h)).read()
-        names |= set(re.findall(r"^\s*(?:int|const char \*)\s*(dsr_\w+)\s*\(", text, re.M))
+        names |= set(re.findall(r"^\s*(?:int|uint32_t|const char \*)\s*(dsr_\w+)\s*\(", text, re.M))
     return names
 
 
@@ -40,7 +40,7 @@ def test_bad_configs():
                      ({"max_teams": 0}, D.DSR_E_INVAL), ({"lds_slab_bytes": 20}, D.DSR_E_INVAL),
                      ({"lds_slab_bytes": 160 * 1024}, D.DSR_E_LDS),
                      ({"hbm_slab_bytes": 17}, D.DSR_E_INVAL), ({"flags": 8}, D.DSR_E_INVAL),
-                     ({"flags": 4}, D.DSR_E_INVAL)]:
+                     ({"flags": 16}, D.DSR_E_INVAL)]:
         with pytest.raises(D.DsrError) as e:
             host_ctx(**kw)
         assert e.value.code == code, kw
@@ -158,4 +158,51 @@ def test_dynamic_tail_validation():
     D.dsr_pop(r, g)
     D.dsr_pop(r, f)
     D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+
+
+def test_publish_list_validation():
+    """Host checks of dsr_publish_list, with the simulator's code where it
+    has the same case."""
+    ctx = host_ctx()
+    r = D.dsr_region_begin(ctx, 2)
+    f = D.dsr_push(r, 24 + 8 * 2 + 4 * 3)          # slot, 2 fp64, 3 int32
+    good = [(f, 0), (f, 40), (f, 44), (f, 48), (f, 24), (f, 32)]
+    kw = dict(inp=0x1000, out=0x2000, ni=3, nf=2)
+    bad = [
+        (good[:-1], {}, D.DSR_E_INVAL),                              # one reference short
+        ([(f, 0), (f, 40), (f, 44), (f, 48), (f, 26), (f, 32)], {}, D.DSR_E_INVAL),  # fp64 misaligned
+        ([(f, 0), (f, 40), (f, 44), (f, 60), (f, 24), (f, 32)], {}, D.DSR_E_INVAL),  # outside the frame
+        ([(f + 1, 0)] + good[1:], {}, D.DSR_E_STATE),                 # no such frame
+        (good, {"body": D.DSR_BODY_FMA_CHAIN}, D.DSR_E_INVAL),        # body takes a frame
+    ]
+    for refs, extra, code in bad:
+        body = extra.get("body", D.DSR_BODY_FMA_CHAIN_REFS)
+        with pytest.raises(D.DsrError) as e:
+            D.dsr_publish_list(r, refs, body, 8, **kw)
+        assert e.value.code == code, (refs, extra)
+    with pytest.raises(D.DsrError) as e:                              # fma_chain_refs needs a list
+        D.dsr_publish(r, f, D.DSR_BODY_FMA_CHAIN_REFS, 8, **kw)
+    assert e.value.code == D.DSR_E_INVAL
+    D.dsr_publish_list(r, good, D.DSR_BODY_FMA_CHAIN_REFS, 8, **kw)
+    D.dsr_pop(r, f)
+    with pytest.raises(D.DsrError) as e:                              # frame popped
+        D.dsr_publish_list(r, good, D.DSR_BODY_FMA_CHAIN_REFS, 8, **kw)
+    assert e.value.code == D.DSR_E_STATE
+    D.dsr_region_free(r)
+    # the simulator reports the same codes for a popped frame and a reference
+    # outside its frame
+    x = np.zeros(8, np.float32)
+    for refs, prog_tail, code in [(good, "popped", "STATE"),
+                                  ([(0, 0), (0, 40), (0, 44), (0, 60), (0, 24), (0, 32)], "", "INVAL")]:
+        refs = [(0, o) for _, o in refs]
+        prog = [S.Push(52)]
+        if prog_tail == "popped":
+            prog.append(S.Pop(0))
+        prog.append(S.PublishList(refs, "fma_chain_refs", {"n": 8, "x": x, "y": np.zeros(8), "ni": 3, "nf": 2}))
+        if prog_tail != "popped":
+            prog.append(S.Pop(0))
+        tr, _ = S.run_region(prog, 1)
+        assert tr[0].error == code
+    assert D.dsr_control_bytes(256) == 64 + 16 * 16 + 20 * 8 + 4 * 32 + 4 * 64
     D.dsr_destroy(ctx)

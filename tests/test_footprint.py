@@ -91,13 +91,13 @@ def test_library_model_gfx950():
     m = D.dsr_hw_model(compute_units=256, regs_per_cu=4 * 512 * 64, reg_granule=8,
                        max_teams_per_cu=32, max_threads_per_cu=2048, shared_per_cu=163840,
                        shared_granule=128, simds_per_cu=4, wave_size=64)
-    o = D.dsr_occupancy(m, 256, 158, 704 + 4096)
+    o = D.dsr_occupancy(m, 256, 158, 864 + 4096)
     assert o["teams_by_registers"] == 3 and o["teams_per_cu"] == 3 and o["limiter"] == "registers"
-    o = D.dsr_occupancy(m, 256, 158, 704 + 131072)
+    o = D.dsr_occupancy(m, 256, 158, 864 + 131072)
     assert o["teams_per_cu"] == 1 and o["limiter"] == "shared"
     # 184 registers: 2 waves per SIMD, 8 per CU, so 4 two-wave teams; one
     # pooled file would hold 131072 / (184 * 128) = 5 of them
-    o = D.dsr_occupancy(m, 128, 184, 704 + 16384)
+    o = D.dsr_occupancy(m, 128, 184, 864 + 16384)
     assert o["teams_by_registers"] == 4 and o["teams_per_cu"] == 4
     m.simds_per_cu = 0
-    assert D.dsr_occupancy(m, 128, 184, 704 + 16384)["teams_by_registers"] == 5
+    assert D.dsr_occupancy(m, 128, 184, 864 + 16384)["teams_by_registers"] == 5

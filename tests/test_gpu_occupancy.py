@@ -8,9 +8,10 @@ from paper_1711_10413_amd import dsr as D  # noqa: E402
 
 
 @pytest.mark.parametrize("wg,lds,variant", [(256, 4096, 0), (256, 4096, 2), (256, 32768, 0),
-                                            (256, 65536, 1), (256, 163840 - 704, 0),
+                                            (256, 65536, 1), (256, 163840 - 864, 0),
                                             (1024, 8192, 0), (128, 16384, 0), (64, 0, 0)])
 def test_model_matches_runtime(wg, lds, variant):
+    assert D.dsr_control_bytes(256) == 864
     ctx = D.dsr_init(wg_size=wg, lds_slab_bytes=lds, hbm_slab_bytes=4096, max_teams=4)
     o = D.dsr_region_occupancy(ctx, variant)
     print(wg, lds, variant, o)

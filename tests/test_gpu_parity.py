@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 from paper_1711_10413_amd import dsr as D  # noqa: E402
 
-LDS_MAX4 = 163840 - 704          # LDS stack that fills a 4-wave team's 160 KiB
+LDS_MAX4 = 163840 - D.dsr_control_bytes(256)   # LDS stack that fills a 4-wave team's 160 KiB
 
 
 def say(*a):
@@ -326,6 +326,27 @@ def test_runtime_chain_frame_in_hbm():
     assert st == 0
     assert D.dsr_region_trace(r, 0)["placements"][0][0] == "hbm"
     check_fma(r, x_np, s_i, s_f, y, arr)
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+
+
+@pytest.mark.parametrize("teams", [1, 33, 511, 512, 513, 1000, 4000])
+def test_cross_team_combine_team_counts(teams):
+    """Exact reduction across team counts on both sides of the one-round
+    combine limit (512) and with ragged arrival groups."""
+    say("combine teams", teams)
+    s_i, s_f, arr, x_np = rt_inputs(3, 2, 0, teams * 97 + 13, seed=7)
+    ctx = D.dsr_init(wg_size=256, lds_slab_bytes=1024, hbm_slab_bytes=256, max_teams=4096)
+    x = torch.from_numpy(x_np).cuda()
+    y = torch.zeros(x.numel(), dtype=torch.float64, device="cuda")
+    st, r = fma_region(ctx, teams, s_i, s_f, x, y)
+    assert st == 0
+    check_fma(r, x_np, s_i, s_f, y)
+    y.zero_()
+    torch.cuda.synchronize()
+    D.dsr_launch(r, stream())           # the arrival counters reset themselves
+    assert D.dsr_region_sync(r) == 0
+    check_fma(r, x_np, s_i, s_f, y)
     D.dsr_region_free(r)
     D.dsr_destroy(ctx)
 
