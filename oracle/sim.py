@@ -596,6 +596,8 @@ def publish_list(team, pushed, op, rng, interleaving):
         f = pushed[idx]
         if off < 0 or off + nb > f.nbytes:
             raise SimError("INVAL", "reference outside its frame")
+        if off % (8 if nb in (8, SLOT_F64_EXACT) else 4):
+            raise SimError("INVAL", "reference not naturally aligned")
         entries.append(struct.pack("<II", SPACE_CODE[f.space], f.off + off))
     n = len(entries)
     if n <= REF_LIST_ENTRIES:

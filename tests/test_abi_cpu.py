@@ -206,3 +206,31 @@ def test_publish_list_validation():
         assert tr[0].error == code
     assert D.dsr_control_bytes(256) == 64 + 16 * 16 + 20 * 8 + 4 * 32 + 4 * 64
     D.dsr_destroy(ctx)
+
+
+@pytest.mark.parametrize("ni,nf,alen,lds,flags", [(4, 4, 0, 4096, 0), (10, 9, 33, 4096, 0), (32, 32, 0, 4096, 0),
+                                                  (32, 31, 100, 8192, 0), (8, 8, 0, 4096, 4), (16, 4, 50, 0, 0)])
+def test_list_programs_pass_host_checks(ni, nf, alen, lds, flags):
+    """The GPU list tests' programs, through a host-only context."""
+    ctx = host_ctx(wg_size=256, lds_slab_bytes=lds, hbm_slab_bytes=8192, max_teams=64, flags=flags | 1)
+    size, aoff = S.fma_chain_layout(ni, nf, alen)
+    refs = [(0, 0)] + [(0, 24 + 8 * nf + 4 * k) for k in range(ni)] + [(0, 24 + 8 * k) for k in range(nf)]
+    if alen:
+        refs.append((0, aoff))
+    r = D.dsr_region_begin(ctx, 5)
+    f = D.dsr_push(r, size)
+    D.dsr_publish_list(r, refs, D.DSR_BODY_FMA_CHAIN_REFS, 100003, inp=0x1000, out=0x2000, ni=ni, nf=nf, alen=alen)
+    D.dsr_pop(r, f)
+    D.dsr_region_free(r)
+    # three frames: scalars (fp64 after 8-byte padding), array, slot
+    r = D.dsr_region_begin(ctx, 4)
+    f0 = D.dsr_push(r, 5 * 4 + 4 + 3 * 8)
+    f1 = D.dsr_push(r, 4 * 3000)
+    f2 = D.dsr_push(r, 24)
+    refs = [(f2, 0)] + [(f0, 4 * k) for k in range(5)] + [(f0, 24 + 8 * k) for k in range(3)] + [(f1, 0)]
+    D.dsr_publish_list(r, refs, D.DSR_BODY_FMA_CHAIN_REFS, 77777, inp=0x1000, out=0x2000, ni=5, nf=3, alen=3000)
+    D.dsr_pop(r, f2)
+    D.dsr_pop(r, f1)
+    D.dsr_pop(r, f0)
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)

@@ -109,8 +109,8 @@ def test_list_across_frames_and_spaces():
     """Slot, scalars and array in three frames, the array in HBM."""
     ni, nf, alen, n = 5, 3, 3000, 77777
     s_i, s_f, arr, x_np = chain_inputs(ni, nf, alen, n, seed=22)
-    scal = struct.pack("<%di" % ni, *s_i) + struct.pack("<%dd" % nf, *s_f)
-    refs = ([(2, 0)] + [(0, 4 * k) for k in range(ni)] + [(0, 4 * ni + 8 * k) for k in range(nf)]
+    scal = struct.pack("<%di" % ni, *s_i) + bytes(4) + struct.pack("<%dd" % nf, *s_f)
+    refs = ([(2, 0)] + [(0, 4 * k) for k in range(ni)] + [(0, 24 + 8 * k) for k in range(nf)]
             + [(1, 0)])
     ctx = D.dsr_init(wg_size=256, lds_slab_bytes=1024, hbm_slab_bytes=16384, max_teams=64,
                      flags=D.DSR_F_TRACE)

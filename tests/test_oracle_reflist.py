@@ -60,9 +60,9 @@ def test_list_spanning_frames_and_spaces():
     memory: the references reach each where it is."""
     ni, nf, alen, n = 3, 2, 50, 177
     s_i, s_f, arr, x = chain_inputs(ni, nf, alen, n, seed=12)
-    scal = struct.pack("<%di" % ni, *s_i) + struct.pack("<%dd" % nf, *s_f)
+    scal = struct.pack("<%di" % ni, *s_i) + bytes(4) + struct.pack("<%dd" % nf, *s_f)
     y = np.zeros(n)
-    refs = ([(2, 0)] + [(0, 4 * k) for k in range(ni)] + [(0, 4 * ni + 8 * k) for k in range(nf)]
+    refs = ([(2, 0)] + [(0, 4 * k) for k in range(ni)] + [(0, 16 + 8 * k) for k in range(nf)]
             + [(1, 0)])
     prog = [S.Push(len(scal), scal), S.Push(4 * alen, arr.tobytes()), S.Push(24),
             S.PublishList(refs, "fma_chain_refs", {"n": n, "x": x, "y": y, "ni": ni, "nf": nf, "alen": alen}),
@@ -112,6 +112,8 @@ def test_bad_references():
         ([S.Push(size, init), S.PublishList([(0, 0), (0, size - 2), (0, 0), (0, 0)], "fma_chain_refs", loop),
           S.Pop(0)], "INVAL"),
         ([S.Push(size, init), S.PublishList(refs[:-1], "fma_chain_refs", loop), S.Pop(0)], "INVAL"),
+        ([S.Push(size, init), S.PublishList([(0, 0), (0, 36), (0, 40), (0, 28)], "fma_chain_refs", loop),
+          S.Pop(0)], "INVAL"),                                   # fp64 not 8-byte aligned
         ([S.Push(size, init), S.PublishList(refs, "fma_chain", loop), S.Pop(0)], "INVAL"),
     ]
     for prog, code in cases:
