@@ -487,10 +487,11 @@ def run_batched(torch, np, D, W, stream, n_inst=10000, seed=3, sample=64):
     algo = 12.0 * total_elems
     cands = []
     for wg in (128, 256, 512, 1024):
-        for lds in (16384, 40960, 65536):
-            for thr in (0, 8192):
-                cands.append(dict(wg_size=wg, lds_slab_bytes=lds, overflow_threshold=thr,
-                                  master_joins=1 if wg >= 512 else 0, use_graph=1))
+        for joins in ((0, 1) if wg <= 512 else (0,)):
+            for lds in (16384, 40960, 65536):
+                for thr in (0, 8192):
+                    cands.append(dict(wg_size=wg, lds_slab_bytes=lds, overflow_threshold=thr,
+                                      master_joins=joins, use_graph=1))
     best, ms = D.dsr_autotune(b, cands, reps=2, stream=stream)
     say("autotune best", best)
 
@@ -546,7 +547,8 @@ def run_served(torch, np, D, W, stream, rates, seconds, pool=1000, seed=4, slots
     x = fill_x(torch, W, Ls, offs, seed, dev)
     y = torch.empty(int(offs[-1]), dtype=torch.float64, device=dev)
     ctx = D.dsr_init(wg_size=256, lds_slab_bytes=32768, hbm_slab_bytes=65536, max_teams=4096)
-    chunk = 65536
+    # a request's teams: one per 16384 elements (up to 64), for latency
+    chunk = 16384
     regs, insts = build_programs(D, W, ctx, Ls, Fs, offs, seed, x.data_ptr(), y.data_ptr(), chunk)
     slot_y = [torch.empty(1 << 20, dtype=torch.float64, device=dev) for _ in range(slots)]
     torch.cuda.synchronize()

@@ -70,7 +70,9 @@ struct cb_header {
     uint32_t bad;      /* OR of the workers' range flags           */
     uint32_t region;   /* launch-specific context published with the */
     uint32_t team;     /* body: which region and which of its teams  */
-    uint32_t pad[4];
+    uint32_t blocks;   /* blocks of the team's range claimed so far by its
+                          waves (balanced split; reset at each publish) */
+    uint32_t pad[3];
 };
 
 /* Bytes of control block for a team of nw waves. */
@@ -217,6 +219,7 @@ __device__ inline void publish(team_t &T, frame_t f, uint32_t body, uint32_t loo
         h->off = f.off;
         h->size = f.size;
         h->loop = loop;
+        h->blocks = 0;
     }
     __syncthreads();
 }

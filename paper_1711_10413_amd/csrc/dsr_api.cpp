@@ -410,7 +410,7 @@ static int upload(dsr_region *r)
     const size_t ops_b = r->ops.size() * sizeof(dsr_op);
     const size_t loops_b = (r->loops.empty() ? 1 : r->loops.size()) * sizeof(dsr_dloop);
     const size_t init_b = r->init.empty() ? 16 : r->init.size();
-    const size_t part_b = (size_t)(r->n_red ? r->n_red : 1) * r->teams * 3 * sizeof(uint64_t);
+    const size_t part_b = (size_t)(r->n_red ? r->n_red : 1) * r->teams * DSR_PART_WORDS * sizeof(uint64_t);
     if (hipMalloc((void **)&r->d_ops, ops_b ? ops_b : sizeof(dsr_op)) != hipSuccess ||
         hipMalloc((void **)&r->d_loops, loops_b) != hipSuccess ||
         hipMalloc((void **)&r->d_init, init_b) != hipSuccess ||
@@ -622,7 +622,7 @@ extern "C" int dsr_batch_create(dsr_ctx *ctx, dsr_region *const *regions, int32_
     sz = align256(sz);
     for (int32_t i = 0; i < n; ++i) {
         o_part[i] = sz;
-        sz += (size_t)(regions[i]->n_red ? regions[i]->n_red : 1) * regions[i]->teams * 3 * sizeof(uint64_t);
+        sz += (size_t)(regions[i]->n_red ? regions[i]->n_red : 1) * regions[i]->teams * DSR_PART_WORDS * sizeof(uint64_t);
     }
     sz = align256(sz);
     const size_t o_res = sz;
@@ -1094,7 +1094,7 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
     const size_t blk = o_recs + align256((size_t)c.slots * sizeof(dsr_drec));
     const size_t slot_h = align256(DSR_SERVE_MAX_OPS * sizeof(dsr_op)) +
                           align256(DSR_SERVE_MAX_LOOPS * sizeof(dsr_dloop)) + align256(c.slot_bytes);
-    const size_t part_b = align256((size_t)DSR_MAX_RED * c.max_teams * 3 * sizeof(uint64_t));
+    const size_t part_b = align256((size_t)DSR_MAX_RED * c.max_teams * DSR_PART_WORDS * sizeof(uint64_t));
     const size_t slot_d = part_b + align256(sizeof(dsr_dresult));
     if (hipSetDevice(ctx->device) != hipSuccess) { delete S; return DSR_E_HIP; }
     if (hipHostMalloc((void **)&S->h_block, blk, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {

@@ -9,6 +9,7 @@
 
 #define DSR_MAX_RED 8
 #define DSR_MAX_OPS 64
+#define DSR_PART_WORDS 4   /* a 192-bit partial: four 48-bit limbs, each with a 16-bit launch tag */
 #define DSR_MAX_LOOPS 16
 #define DSR_ARRIVE_GROUPS 32
 
@@ -58,7 +59,7 @@ struct dsr_dregion {
     const dsr_op *ops;
     const dsr_dloop *loops;
     const uint8_t *init;
-    uint64_t *partials;    /* [n_red][teams][3] */
+    uint64_t *partials;    /* [n_red][teams][DSR_PART_WORDS] tagged limbs */
     dsr_dresult *result;
     uint32_t *trace;       /* [teams][DSR_TRACE_WORDS] or null */
     uint32_t n_ops;

@@ -243,10 +243,43 @@ struct span_t {
  * device counter (the next claim is issued before the current block runs,
  * so its latency overlaps the work).  Claimed blocks are shared by the 64
  * lanes of the claiming wave. */
+/* Balanced split of a team's static range among its waves: the range is
+ * cut into blocks of DSR_TEAM_BLOCK iterations that the waves claim from a
+ * counter in the team's LDS control block, so a wave whose SIMD it shares
+ * with fewer others takes more blocks.  Used for the long fma chains, which
+ * are bound by the SIMDs' fp64 rate: with three worker waves per team and
+ * two teams per CU, some SIMDs hold two worker waves and some one. */
+#define DSR_TEAM_BLOCK 2048u
+
+template <class F>
+__device__ __forceinline__ void team_blocks(span_t sp, uint32_t lane, lane_acc &A, F &&f)
+{
+    LDSQ uint32_t *ctr = (LDSQ uint32_t *)(dsr_lds + offsetof(cb_header, blocks));
+    const uint64_t lo = sp.lo;
+    const uint32_t nblk = sp.hi > lo ? (uint32_t)((sp.hi - lo + DSR_TEAM_BLOCK - 1) / DSR_TEAM_BLOCK) : 0u;
+    uint32_t c = 0;
+    if (lane == 0) c = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    c = uniform((uint32_t)__shfl((int)c, 0, 64));
+    uint32_t since = 0;
+    while (c < nblk) {
+        uint32_t cn = 0;
+        if (lane == 0) cn = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const uint64_t b = lo + (uint64_t)c * DSR_TEAM_BLOCK;
+        f(span_t{b, min(sp.hi, b + DSR_TEAM_BLOCK), lane, 64u});
+        /* a block adds 32 values per lane: flush well before 2^16 */
+        if (++since == 256) { acc_flush(A); since = 0; }
+        c = uniform((uint32_t)__shfl((int)cn, 0, 64));
+    }
+}
+
 template <class F>
 __device__ __forceinline__ void for_spans(const dsr_dloop &L, span_t sp, uint32_t lane,
-                                          uint32_t *claim, lane_acc &A, F &&f)
+                                          uint32_t *claim, lane_acc &A, F &&f, bool balanced = false)
 {
+    if (balanced && L.schedule == DSR_SCHED_STATIC) {
+        team_blocks(sp, lane, A, f);
+        return;
+    }
     f(sp);
     if (L.schedule != DSR_SCHED_DYNAMIC_TAIL) return;
     uint32_t c = 0;
@@ -378,7 +411,7 @@ __device__ __forceinline__ void fma_fixed_spans(const double (&s)[NI + NF], cons
 {
     const GLB float *x = (const GLB float *)L.in;
     GLB double *y = (GLB double *)L.out;
-    for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_span<NI, NF>(s, x, y, q, A); });
+    for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_span<NI, NF>(s, x, y, q, A); }, NI + NF >= 24);
 }
 
 template <int NI, int NF>
@@ -593,10 +626,13 @@ __device__ __forceinline__ void rt_spans(const SC &sc, AP arr, const dsr_dloop &
 {
     const GLB float *x = (const GLB float *)L.in;
     GLB double *y = (GLB double *)L.out;
+    const bool balanced = uniform(L.ni + L.nf) >= 24;
     if (alen)
-        for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_rt_span<U, true>(sc, arr, alen, x, y, q, A); });
+        for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_rt_span<U, true>(sc, arr, alen, x, y, q, A); },
+                  balanced);
     else
-        for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_rt_span<U, false>(sc, arr, alen, x, y, q, A); });
+        for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_rt_span<U, false>(sc, arr, alen, x, y, q, A); },
+                  balanced);
 }
 
 /* Body entry for the run-time chain, frame in LDS (offset `off` in the
@@ -649,13 +685,27 @@ __device__ __forceinline__ void gather_vectors(AP arr, const dsr_dloop &L, uint6
     GLB i32x4 *__restrict__ out4 = (GLB i32x4 *)L.out;
     uint32_t idx = (uint32_t)((v0 * 4) % len);
     const uint32_t step = (uint32_t)((stride * 4) % len);
-    for (uint64_t v = v0; v < v1; v += stride) {
+    uint64_t v = v0;
+    /* four vectors at a time, their array reads (LDS or global) all in flight */
+    for (; v + 3 * stride < v1; v += 4 * stride) {
+        const uint32_t i1 = mod_step(idx, step, len), i2 = mod_step(i1, step, len), i3 = mod_step(i2, step, len);
+        i32x4 s[4] = {gather4<NA>(arr, len, L.arrays, idx), gather4<NA>(arr, len, L.arrays, i1),
+                      gather4<NA>(arr, len, L.arrays, i2), gather4<NA>(arr, len, L.arrays, i3)};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint64_t w = v + u * stride;
+            const uint32_t base = (uint32_t)(w * 4);
+            s[u] += i32x4{(int32_t)base, (int32_t)(base + 1), (int32_t)(base + 2), (int32_t)(base + 3)};
+            __builtin_nontemporal_store(s[u], &out4[w]);
+        }
+        idx = mod_step(i3, step, len);
+    }
+    for (; v < v1; v += stride) {
         i32x4 s = gather4<NA>(arr, len, L.arrays, idx);
         const uint32_t base = (uint32_t)(v * 4);
         s += i32x4{(int32_t)base, (int32_t)(base + 1), (int32_t)(base + 2), (int32_t)(base + 3)};
         __builtin_nontemporal_store(s, &out4[v]);
-        idx += step;
-        if (idx >= len) idx -= len;
+        idx = mod_step(idx, step, len);
     }
 }
 
@@ -739,6 +789,40 @@ __device__ __forceinline__ uint64_t load_dev(const uint64_t *p)
 }
 
 __device__ __forceinline__ void drain_memory() { __builtin_amdgcn_s_waitcnt(0); }
+
+/* Cross-team partials travel as four 48-bit limbs, each word carrying a
+ * 16-bit tag of the launch that wrote it (a group sum sets the tag's top
+ * bit).  Every word is stored with one 64-bit store, so a reader that sees
+ * this launch's tag in all four words has the whole partial: a team need
+ * not wait for its partial to land before it arrives, and the combining
+ * team re-reads any word that still shows an older tag. */
+#define DSR_LIMB_MASK ((1ull << 48) - 1)
+#define DSR_TAG_GROUP 0x8000u
+
+__device__ __forceinline__ void store_partial(uint64_t *p, i192 v, uint32_t tag)
+{
+    const uint64_t t = (uint64_t)tag << 48;
+    store_dev(p, (v.w0 & DSR_LIMB_MASK) | t);
+    store_dev(p + 1, (((v.w0 >> 48) | (v.w1 << 16)) & DSR_LIMB_MASK) | t);
+    store_dev(p + 2, (((v.w1 >> 32) | (v.w2 << 32)) & DSR_LIMB_MASK) | t);
+    store_dev(p + 3, ((v.w2 >> 16) & DSR_LIMB_MASK) | t);
+}
+
+__device__ __forceinline__ i192 limbs_value(uint64_t a, uint64_t b, uint64_t c, uint64_t d)
+{
+    a &= DSR_LIMB_MASK;
+    b &= DSR_LIMB_MASK;
+    c &= DSR_LIMB_MASK;
+    d &= DSR_LIMB_MASK;
+    return i192{a | (b << 48), (b >> 16) | (c << 32), (c >> 32) | (d << 16)};
+}
+
+__device__ __forceinline__ bool tagged(uint64_t w, uint32_t tag) { return (uint32_t)(w >> 48) == tag; }
+
+/* Waits on a partial that is still in flight are bounded; past the bound
+ * the region reports DSR_E_STATE instead of hanging (it would mean a lost
+ * store, an internal error). */
+#define DSR_PARTIAL_SPINS (1u << 22)
 
 /* ---- region execution ---------------------------------------------------- */
 __device__ __forceinline__ const uint8_t *frame_ptr(const team_t &T, frame_t f)
@@ -904,25 +988,53 @@ __device__ __forceinline__ void participate(team_t &T, const dsr_dregion &R, con
     end_parallel(T, w.w0, w.w1, w.w2, bad);
 }
 
-/* Copy a frame's initial bytes (or zeros) with the whole master wave. */
+/* Bytes o .. o+3 of src as a little-endian word, zero from `lim` on. */
+__device__ __forceinline__ uint32_t ragged_word(const uint8_t *src, uint32_t o, uint32_t lim)
+{
+    uint32_t w = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q)
+        if (o + q < lim) w |= (uint32_t)src[o + q] << (8 * q);
+    return w;
+}
+
+/* Copy a frame's initial bytes (or zeros) with the whole master wave.  The
+ * 16-byte vectors that lie wholly inside the initial bytes go in rounds of
+ * eight per lane, all loads of a round in flight together (a 32 KiB frame
+ * is four round trips, not thirty-two); the rest is zeros or a ragged
+ * edge. */
 __device__ __forceinline__ void init_frame(team_t &T, frame_t f, const uint8_t *src, uint32_t init_bytes,
-                           uint32_t nbytes)
+                                           uint32_t nbytes)
 {
     uint8_t *dst = (uint8_t *)frame_ptr(T, f);
     const uint32_t nvec = nbytes >> 4;
     const bool src_aligned = (((uintptr_t)src) & 15u) == 0;
-    for (uint32_t k = T.lane; k < nvec; k += 64) {
+    const uint32_t full = src_aligned ? min(init_bytes, nbytes) >> 4 : 0;
+    const uint4 *s4 = (const uint4 *)src;
+    uint4 *d4 = (uint4 *)dst;
+    for (uint32_t k0 = T.lane; k0 < full; k0 += 512) {
+        const uint32_t k1 = k0 + 64, k2 = k0 + 128, k3 = k0 + 192, k4 = k0 + 256, k5 = k0 + 320,
+                       k6 = k0 + 384, k7 = k0 + 448;
+        /* indices past the end reload the last vector (always in bounds);
+         * their stores are skipped */
+        const uint32_t last = full - 1;
+        const uint4 v0 = s4[k0];
+        const uint4 v1 = s4[min(k1, last)], v2 = s4[min(k2, last)], v3 = s4[min(k3, last)];
+        const uint4 v4 = s4[min(k4, last)], v5 = s4[min(k5, last)], v6 = s4[min(k6, last)];
+        const uint4 v7 = s4[min(k7, last)];
+        d4[k0] = v0;
+        if (k1 < full) d4[k1] = v1;
+        if (k2 < full) d4[k2] = v2;
+        if (k3 < full) d4[k3] = v3;
+        if (k4 < full) d4[k4] = v4;
+        if (k5 < full) d4[k5] = v5;
+        if (k6 < full) d4[k6] = v6;
+        if (k7 < full) d4[k7] = v7;
+    }
+    for (uint32_t k = full + T.lane; k < nvec; k += 64) {
         const uint32_t o = k * 16;
-        uint4 v;
-        if (o + 16 <= init_bytes && src_aligned) {
-            v = *(const uint4 *)(src + o);
-        } else {
-            uint8_t tmp[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) tmp[q] = (o + q < init_bytes) ? src[o + q] : 0;
-            v = *(const uint4 *)tmp;
-        }
-        *(uint4 *)(dst + o) = v;
+        d4[k] = make_uint4(ragged_word(src, o, init_bytes), ragged_word(src, o + 4, init_bytes),
+                           ragged_word(src, o + 8, init_bytes), ragged_word(src, o + 12, init_bytes));
     }
     for (uint32_t o = nvec * 16 + T.lane; o < nbytes; o += 64) dst[o] = o < init_bytes ? src[o] : 0;
 }
@@ -970,15 +1082,15 @@ __device__ __forceinline__ dsr_op op_at(const op_lanes &o, uint32_t k)
  * (Figure 2): pushes, publishes and pops.  Returns the team's error. */
 template <int VARIANT>
 __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, const dsr_dconfig &C,
-                                               uint32_t region, uint32_t team, uint32_t &barriers,
-                                               uint32_t &inner_pushes)
+                                               uint32_t region, uint32_t team, uint32_t tag,
+                                               uint32_t &barriers, uint32_t &inner_pushes)
 {
     cb_header *h = header(T);
     uint32_t *tr = (C.trace && R.trace) ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
     if (tr && T.lane == 0) tr[86] = (uint32_t)wall_clock64();
     wave_sync();
     int32_t err = 0;
-    uint32_t npush = 0;
+    uint32_t npush = 0, nred = 0;
     bool stamped = false;
     const uint32_t nwork = C.master_joins ? T.nw : T.nw - 1;
     const uint32_t n_ops = min(uniform(R.n_ops), (uint32_t)DSR_MAX_OPS);
@@ -1096,12 +1208,9 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
                         cw[0] = sv.w0; cw[1] = sv.w1; cw[2] = sv.w2;
                     }
                 }
-                if (T.lane == 0) {
-                    uint64_t *pp = R.partials + ((uint64_t)op.red * R.teams + team) * 3;
-                    store_dev(pp, sv.w0);
-                    store_dev(pp + 1, sv.w1);
-                    store_dev(pp + 2, sv.w2);
-                }
+                if (T.lane == 0)
+                    store_partial(R.partials + ((uint64_t)op.red * R.teams + team) * DSR_PART_WORDS, sv, tag);
+                nred = op.red + 1;
             }
             wave_sync();
             /* a global reference list dies with its parallel region */
@@ -1123,39 +1232,60 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
         tr[0] = npush;
         tr[81] = (uint32_t)err;
     }
-    if (err && T.lane == 0) atomicCAS(&R.result->error, 0, err);
+    if (err && T.lane == 0) {
+        atomicCAS(&R.result->error, 0, err);
+        /* a failed team still tags every reduction's partial (as zero), so
+         * the combining team sees all partials of this launch */
+        for (uint32_t r = nred; r < R.n_red; ++r)
+            store_partial(R.partials + ((uint64_t)r * R.teams + team) * DSR_PART_WORDS, i192{0, 0, 0}, tag);
+    }
     return err;
 }
 
-/* Sum `cnt` 192-bit partials (three words each, `stride` partials apart)
- * with the whole wave: each lane issues up to eight independent loads per
- * round, so up to 512 partials cost one memory round trip. */
-__device__ __forceinline__ i192 sum_partials(const uint64_t *base, uint32_t cnt, uint32_t stride, uint32_t lane)
+/* Sum `cnt` tagged partials (`stride` partials apart) with the whole wave:
+ * each lane issues PU partials' loads per round (eight: up to 512 partials
+ * in one memory round trip); words that still show an older tag are read
+ * again.  ok turns false if a partial never arrives. */
+template <int PU>
+__device__ __forceinline__ i192 sum_partials(const uint64_t *base, uint32_t cnt, uint32_t stride, uint32_t lane,
+                                             uint32_t tag, bool &ok)
 {
     i192 s{0, 0, 0};
-    for (uint32_t j0 = 0; j0 < cnt; j0 += 512) {
-        uint64_t w[8][3];
+    for (uint32_t j0 = 0; j0 < cnt; j0 += 64 * PU) {
+        uint64_t w[PU][4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < PU; ++u) {
             const uint32_t j = j0 + 64u * u + lane;
-            const uint64_t *pp = base + 3ull * j * stride;
+            const uint64_t *pp = base + (uint64_t)DSR_PART_WORDS * j * stride;
             const bool in = j < cnt;
-            w[u][0] = in ? load_dev(pp) : 0;
-            w[u][1] = in ? load_dev(pp + 1) : 0;
-            w[u][2] = in ? load_dev(pp + 2) : 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) w[u][q] = in ? load_dev(pp + q) : ((uint64_t)tag << 48);
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s = add192(s, i192{w[u][0], w[u][1], w[u][2]});
+        for (int u = 0; u < PU; ++u) {
+            const uint32_t j = j0 + 64u * u + lane;
+            const uint64_t *pp = base + (uint64_t)DSR_PART_WORDS * j * stride;
+            uint32_t spins = 0;
+            while (!(tagged(w[u][0], tag) && tagged(w[u][1], tag) && tagged(w[u][2], tag) && tagged(w[u][3], tag))) {
+                if (++spins > DSR_PARTIAL_SPINS) { ok = false; break; }
+                __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) w[u][q] = load_dev(pp + q);
+            }
+            if (j < cnt) s = add192(s, limbs_value(w[u][0], w[u][1], w[u][2], w[u][3]));
+        }
     }
     return wave_sum192(s);
 }
 
 /* Last team: the region's reductions from the (group) partials, exact in
  * 192-bit integers, rounded once for fp64. */
-__device__ __forceinline__ void combine_teams(const dsr_dregion &R, uint32_t cnt, uint32_t stride, uint32_t lane)
+template <int PU>
+__device__ __forceinline__ void combine_teams(const dsr_dregion &R, uint32_t cnt, uint32_t stride, uint32_t lane,
+                                              uint32_t tag, bool &ok)
 {
     for (uint32_t r = 0; r < R.n_red; ++r) {
-        const i192 s = sum_partials(R.partials + (uint64_t)r * R.teams * 3, cnt, stride, lane);
+        const i192 s = sum_partials<PU>(R.partials + (uint64_t)r * R.teams * DSR_PART_WORDS, cnt, stride, lane, tag, ok);
         if (lane == 0) {
             R.result->fixed[r][0] = s.w0;
             R.result->fixed[r][1] = s.w1;
@@ -1191,7 +1321,8 @@ __device__ __forceinline__ void publish_record(const dsr_dregion &R, dsr_drec *r
  * reads every partial in one round; with more, the last team of each group
  * first adds up its group's partials and leaves the sum in the group's
  * first partial slot, and the last team overall adds the group sums. */
-__device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team, uint32_t lane,
+template <int PU>
+__device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team, uint32_t lane, uint32_t done0,
                                             uint64_t *done_ts, dsr_drec *rec = nullptr)
 {
     const uint32_t gsize = (R.teams + DSR_ARRIVE_GROUPS - 1) / DSR_ARRIVE_GROUPS;
@@ -1199,7 +1330,8 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team,
     const uint32_t g = team / gsize;
     const uint32_t in_group = min(gsize, R.teams - g * gsize);
     const bool group_sums = R.teams > 512;
-    drain_memory();                      /* this team's partials are stored */
+    const uint32_t tag = (done0 + 1) & 0x7FFFu;
+    bool ok = true;
     uint32_t prev = 0;
     if (lane == 0)
         prev = __hip_atomic_fetch_add(&R.result->group[g * 16], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1209,31 +1341,29 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team,
     if (ngroups > 1) {
         if (group_sums) {
             for (uint32_t r = 0; r < R.n_red; ++r) {
-                uint64_t *gp = R.partials + ((uint64_t)r * R.teams + (uint64_t)g * gsize) * 3;
-                const i192 s = sum_partials(gp, in_group, 1, lane);
-                if (lane == 0) {
-                    store_dev(gp, s.w0);
-                    store_dev(gp + 1, s.w1);
-                    store_dev(gp + 2, s.w2);
-                }
+                uint64_t *gp = R.partials + ((uint64_t)r * R.teams + (uint64_t)g * gsize) * DSR_PART_WORDS;
+                const i192 s = sum_partials<PU>(gp, in_group, 1, lane, tag, ok);
+                if (lane == 0) store_partial(gp, s, tag | DSR_TAG_GROUP);
             }
-            drain_memory();              /* the group sums are stored */
         }
         if (lane == 0)
             prev = __hip_atomic_fetch_add(&R.result->arrived, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         prev = uniform((uint32_t)__shfl((int)prev, 0, 64));
-        if (prev != ngroups - 1) return;
+        if (prev != ngroups - 1) {
+            if (!ok && lane == 0) atomicCAS(&R.result->error, 0, DSR_E_STATE);
+            return;
+        }
         if (lane == 0) __hip_atomic_store(&R.result->arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    if (ngroups > 1 && group_sums) combine_teams<PU>(R, ngroups, gsize, lane, tag | DSR_TAG_GROUP, ok);
+    else combine_teams<PU>(R, R.teams, 1, lane, tag, ok);
     int32_t err = 0;
     if (lane == 0) err = __hip_atomic_exchange(&R.result->error, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (ngroups > 1 && group_sums) combine_teams(R, ngroups, gsize, lane);
-    else combine_teams(R, R.teams, 1, lane);
     if (lane < DSR_MAX_LOOPS)
         __hip_atomic_store(&R.result->claim[lane], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (lane == 0) {
-        R.result->final_error = err;
-        R.result->done += 1;
+        R.result->final_error = err ? err : (ok ? 0 : DSR_E_STATE);
+        __hip_atomic_store(&R.result->done, done0 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (done_ts) *done_ts = wall_clock64();
     }
     if (rec) publish_record(R, rec, lane);
@@ -1383,12 +1513,16 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
                 team_reset(T);
             }
             const dsr_dregion &R = C.serve ? stage_request(T, LP.regions + region) : LP.regions[region];
-            run_program<VARIANT>(T, R, C, region, team, barriers, inner_pushes);
+            /* launches of this region so far: tags this launch's partials */
+            const uint32_t done0 = uniform(__hip_atomic_load(&R.result->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            run_program<VARIANT>(T, R, C, region, team, (done0 + 1) & 0x7FFFu, barriers, inner_pushes);
             uint32_t *tr = (single && C.trace && R.trace) ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
             if (tr && T.lane == 0) tr[87] = (uint32_t)wall_clock64();
             if (C.serve) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); /* outputs out of L2 */
-            finish_team(R, team, T.lane, (LP.done_ts && !LP.published) ? LP.done_ts + region : nullptr,
-                        LP.recs ? LP.recs + region : nullptr);
+            /* the 1024-thread instance reads fewer partials per round */
+            finish_team<VARIANT < 0 ? 2 : 8>(R, team, T.lane, done0,
+                                             (LP.done_ts && !LP.published) ? LP.done_ts + region : nullptr,
+                                             LP.recs ? LP.recs + region : nullptr);
             if (tr && T.lane == 0) tr[88] = (uint32_t)wall_clock64();
         }
         if (LP.exited && T.lane == 0)
