@@ -158,6 +158,12 @@ def run_sweep(torch, np, D, W, args, stream):
         for r in regions2.values():
             D.dsr_region_free(r)
         D.dsr_destroy(ctx2)
+    occupancy = {}
+    for v in sorted({kernel_variant(K) for K in ks}):
+        o = D.dsr_region_occupancy(ctx, v)
+        occupancy["dsr_region_kernel<256, %d>" % v] = {k: o[k] for k in ("teams_per_cu", "limiter", "regs_per_thread",
+                                                                        "shared_per_team", "teams_by_registers",
+                                                                        "teams_by_shared", "hip_teams_per_cu")}
     for r in regions.values():
         D.dsr_region_free(r)
     D.dsr_destroy(ctx)
@@ -170,7 +176,7 @@ def run_sweep(torch, np, D, W, args, stream):
         "per_k_gbs": {K: algo / (ms * 1e-3) / 1e9 for K, ms in by_k.items()},
         "loop_phase_us": loop_us,
         "loop_phase_gbs": {K: algo / (us * 1e-6) / 1e9 for K, us in loop_us.items() if us > 0},
-        "team_phases_us": phases,
+        "team_phases_us": phases, "occupancy": occupancy,
         "lds_bytes_per_team": D.dsr_control_bytes(WG) + 4096, "hbm_only_stack": hbm_only, "verified": verified,
     }
 
@@ -407,8 +413,12 @@ def run_arrays(torch, np, D, W, stream, reps=6):
                 e1.record()
                 torch.cuda.synchronize()
                 ms = e0.elapsed_time(e1) / reps
+                occ = D.dsr_region_occupancy(ctx, 0)
                 row[mode] = {"ms": ms, "gbs": 4.0 * n / (ms * 1e-3) / 1e9,
-                             "frame_in": "lds" if slab else "hbm", "lds_bytes_per_team": D.dsr_control_bytes(WG) + slab}
+                             "frame_in": "lds" if slab else "hbm", "lds_bytes_per_team": D.dsr_control_bytes(WG) + slab,
+                             # array reads: 4 B per array per element, from LDS or from L2/HBM
+                             "array_read_gbs": 4.0 * A * n / (ms * 1e-3) / 1e9,
+                             "teams_per_cu": occ["teams_per_cu"], "occupancy_limiter": occ["limiter"]}
                 if mode == "lds":
                     ok = D.dsr_region_sync(regs[(reps - 1) % 2]) == 0
                     idx = np.random.default_rng(A * 7 + length).integers(0, n, 256)
@@ -681,7 +691,7 @@ def main():
                            "algorithmic_bytes_per_launch": sw["algo_bytes"],
                            "avg_launch_ms": avg_ms}
         for k in ("per_k_kernel_ms", "per_k_gbs", "loop_phase_us", "loop_phase_gbs",
-                  "team_phases_us", "lds_bytes_per_team", "hbm_only_stack", "verified"):
+                  "team_phases_us", "occupancy", "lds_bytes_per_team", "hbm_only_stack", "verified"):
             out[k] = sw[k]
     if "lists" in parts:
         say("lists")

@@ -9,9 +9,11 @@
 
 #define DSR_MAX_RED 8
 #define DSR_MAX_OPS 64
-#define DSR_PART_WORDS 4   /* a 192-bit partial: four 48-bit limbs, each with a 16-bit launch tag */
+#define DSR_PART_WORDS 3   /* a 192-bit partial: three 64-bit words, low first */
 #define DSR_MAX_LOOPS 16
+#ifndef DSR_ARRIVE_GROUPS
 #define DSR_ARRIVE_GROUPS 32
+#endif
 
 enum : uint32_t { DSR_OP_PUSH = 1, DSR_OP_PUBLISH = 2, DSR_OP_POP = 3 };
 
@@ -59,7 +61,7 @@ struct dsr_dregion {
     const dsr_op *ops;
     const dsr_dloop *loops;
     const uint8_t *init;
-    uint64_t *partials;    /* [n_red][teams][DSR_PART_WORDS] tagged limbs */
+    uint64_t *partials;    /* [n_red][teams][DSR_PART_WORDS] */
     dsr_dresult *result;
     uint32_t *trace;       /* [teams][DSR_TRACE_WORDS] or null */
     uint32_t n_ops;

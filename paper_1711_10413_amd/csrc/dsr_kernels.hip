@@ -37,7 +37,10 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
 /* Element pairs per lane and batch in the run-time fma chain (256- and
- * 512-thread instances). */
+ * 512-thread instances), and in the fixed chains of up to four scalars. */
+#ifndef DSR_FIXED_U_LIGHT
+#define DSR_FIXED_U_LIGHT 8
+#endif
 #ifndef DSR_RT_PAIRS
 #define DSR_RT_PAIRS 8
 #endif
@@ -245,11 +248,20 @@ struct span_t {
  * lanes of the claiming wave. */
 /* Balanced split of a team's static range among its waves: the range is
  * cut into blocks of DSR_TEAM_BLOCK iterations that the waves claim from a
- * counter in the team's LDS control block, so a wave whose SIMD it shares
- * with fewer others takes more blocks.  Used for the long fma chains, which
- * are bound by the SIMDs' fp64 rate: with three worker waves per team and
- * two teams per CU, some SIMDs hold two worker waves and some one. */
-#define DSR_TEAM_BLOCK 2048u
+ * counter in the team's LDS control block.  A wave then streams contiguous
+ * 8 KiB stretches of x (one batch of eight pairs per lane), and a wave on a
+ * SIMD it shares with fewer others takes more blocks: with three worker
+ * waves per team and two teams per CU some SIMDs hold two worker waves and
+ * some one.  Measured on the fma chains against the fixed per-lane share:
+ * 2.2-2.7 us faster per 2^24-element region for up to 16 scalars, 0.5-1.2 us
+ * for 32 and 64; 2048-, 4096- and 8192-iteration blocks were slower. */
+#ifndef DSR_TEAM_BLOCK
+#define DSR_TEAM_BLOCK 1024u
+#endif
+/* chains of at least this many scalars take the balanced split (all) */
+#ifndef DSR_BALANCE_MIN
+#define DSR_BALANCE_MIN 1
+#endif
 
 template <class F>
 __device__ __forceinline__ void team_blocks(span_t sp, uint32_t lane, lane_acc &A, F &&f)
@@ -342,7 +354,7 @@ __device__ __forceinline__ void fma_span(const double (&s)[NI + NF], const GLB f
     const GLB f32x2 *__restrict__ x2 = (const GLB f32x2 *)x;
     GLB f64x2 *__restrict__ y2 = (GLB f64x2 *)y;
     const uint64_t nv1 = phi >> 1;
-    constexpr int U = (NI + NF >= 64) ? 4 : 8;
+    constexpr int U = (NI + NF >= 64) ? 4 : (NI + NF <= 4 ? DSR_FIXED_U_LIGHT : 8);
     const uint64_t step = (uint64_t)U * sp.P;
     uint64_t v = (plo >> 1) + sp.p;
     if (v + (uint64_t)(U - 1) * sp.P < nv1) {
@@ -411,7 +423,7 @@ __device__ __forceinline__ void fma_fixed_spans(const double (&s)[NI + NF], cons
 {
     const GLB float *x = (const GLB float *)L.in;
     GLB double *y = (GLB double *)L.out;
-    for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_span<NI, NF>(s, x, y, q, A); }, NI + NF >= 24);
+    for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_span<NI, NF>(s, x, y, q, A); }, NI + NF >= DSR_BALANCE_MIN);
 }
 
 template <int NI, int NF>
@@ -626,7 +638,7 @@ __device__ __forceinline__ void rt_spans(const SC &sc, AP arr, const dsr_dloop &
 {
     const GLB float *x = (const GLB float *)L.in;
     GLB double *y = (GLB double *)L.out;
-    const bool balanced = uniform(L.ni + L.nf) >= 24;
+    const bool balanced = uniform(L.ni + L.nf) >= DSR_BALANCE_MIN;
     if (alen)
         for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_rt_span<U, true>(sc, arr, alen, x, y, q, A); },
                   balanced);
@@ -790,39 +802,6 @@ __device__ __forceinline__ uint64_t load_dev(const uint64_t *p)
 
 __device__ __forceinline__ void drain_memory() { __builtin_amdgcn_s_waitcnt(0); }
 
-/* Cross-team partials travel as four 48-bit limbs, each word carrying a
- * 16-bit tag of the launch that wrote it (a group sum sets the tag's top
- * bit).  Every word is stored with one 64-bit store, so a reader that sees
- * this launch's tag in all four words has the whole partial: a team need
- * not wait for its partial to land before it arrives, and the combining
- * team re-reads any word that still shows an older tag. */
-#define DSR_LIMB_MASK ((1ull << 48) - 1)
-#define DSR_TAG_GROUP 0x8000u
-
-__device__ __forceinline__ void store_partial(uint64_t *p, i192 v, uint32_t tag)
-{
-    const uint64_t t = (uint64_t)tag << 48;
-    store_dev(p, (v.w0 & DSR_LIMB_MASK) | t);
-    store_dev(p + 1, (((v.w0 >> 48) | (v.w1 << 16)) & DSR_LIMB_MASK) | t);
-    store_dev(p + 2, (((v.w1 >> 32) | (v.w2 << 32)) & DSR_LIMB_MASK) | t);
-    store_dev(p + 3, ((v.w2 >> 16) & DSR_LIMB_MASK) | t);
-}
-
-__device__ __forceinline__ i192 limbs_value(uint64_t a, uint64_t b, uint64_t c, uint64_t d)
-{
-    a &= DSR_LIMB_MASK;
-    b &= DSR_LIMB_MASK;
-    c &= DSR_LIMB_MASK;
-    d &= DSR_LIMB_MASK;
-    return i192{a | (b << 48), (b >> 16) | (c << 32), (c >> 32) | (d << 16)};
-}
-
-__device__ __forceinline__ bool tagged(uint64_t w, uint32_t tag) { return (uint32_t)(w >> 48) == tag; }
-
-/* Waits on a partial that is still in flight are bounded; past the bound
- * the region reports DSR_E_STATE instead of hanging (it would mean a lost
- * store, an internal error). */
-#define DSR_PARTIAL_SPINS (1u << 22)
 
 /* ---- region execution ---------------------------------------------------- */
 __device__ __forceinline__ const uint8_t *frame_ptr(const team_t &T, frame_t f)
@@ -1082,15 +1061,15 @@ __device__ __forceinline__ dsr_op op_at(const op_lanes &o, uint32_t k)
  * (Figure 2): pushes, publishes and pops.  Returns the team's error. */
 template <int VARIANT>
 __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, const dsr_dconfig &C,
-                                               uint32_t region, uint32_t team, uint32_t tag,
-                                               uint32_t &barriers, uint32_t &inner_pushes)
+                                               uint32_t region, uint32_t team, uint32_t &barriers,
+                                               uint32_t &inner_pushes)
 {
     cb_header *h = header(T);
     uint32_t *tr = (C.trace && R.trace) ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
     if (tr && T.lane == 0) tr[86] = (uint32_t)wall_clock64();
     wave_sync();
     int32_t err = 0;
-    uint32_t npush = 0, nred = 0;
+    uint32_t npush = 0;
     bool stamped = false;
     const uint32_t nwork = C.master_joins ? T.nw : T.nw - 1;
     const uint32_t n_ops = min(uniform(R.n_ops), (uint32_t)DSR_MAX_OPS);
@@ -1208,9 +1187,12 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
                         cw[0] = sv.w0; cw[1] = sv.w1; cw[2] = sv.w2;
                     }
                 }
-                if (T.lane == 0)
-                    store_partial(R.partials + ((uint64_t)op.red * R.teams + team) * DSR_PART_WORDS, sv, tag);
-                nred = op.red + 1;
+                if (T.lane == 0) {
+                    uint64_t *pp = R.partials + ((uint64_t)op.red * R.teams + team) * DSR_PART_WORDS;
+                    store_dev(pp, sv.w0);
+                    store_dev(pp + 1, sv.w1);
+                    store_dev(pp + 2, sv.w2);
+                }
             }
             wave_sync();
             /* a global reference list dies with its parallel region */
@@ -1232,60 +1214,39 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
         tr[0] = npush;
         tr[81] = (uint32_t)err;
     }
-    if (err && T.lane == 0) {
-        atomicCAS(&R.result->error, 0, err);
-        /* a failed team still tags every reduction's partial (as zero), so
-         * the combining team sees all partials of this launch */
-        for (uint32_t r = nred; r < R.n_red; ++r)
-            store_partial(R.partials + ((uint64_t)r * R.teams + team) * DSR_PART_WORDS, i192{0, 0, 0}, tag);
-    }
+    if (err && T.lane == 0) atomicCAS(&R.result->error, 0, err);
     return err;
 }
 
-/* Sum `cnt` tagged partials (`stride` partials apart) with the whole wave:
- * each lane issues PU partials' loads per round (eight: up to 512 partials
- * in one memory round trip); words that still show an older tag are read
- * again.  ok turns false if a partial never arrives. */
-template <int PU>
-__device__ __forceinline__ i192 sum_partials(const uint64_t *base, uint32_t cnt, uint32_t stride, uint32_t lane,
-                                             uint32_t tag, bool &ok)
+/* Sum `cnt` 192-bit partials (three words each, `stride` partials apart)
+ * with the whole wave: each lane issues up to eight independent loads per
+ * round, so up to 512 partials cost one memory round trip. */
+__device__ __forceinline__ i192 sum_partials(const uint64_t *base, uint32_t cnt, uint32_t stride, uint32_t lane)
 {
     i192 s{0, 0, 0};
-    for (uint32_t j0 = 0; j0 < cnt; j0 += 64 * PU) {
-        uint64_t w[PU][4];
+    for (uint32_t j0 = 0; j0 < cnt; j0 += 512) {
+        uint64_t w[8][3];
 #pragma unroll
-        for (int u = 0; u < PU; ++u) {
+        for (int u = 0; u < 8; ++u) {
             const uint32_t j = j0 + 64u * u + lane;
             const uint64_t *pp = base + (uint64_t)DSR_PART_WORDS * j * stride;
             const bool in = j < cnt;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) w[u][q] = in ? load_dev(pp + q) : ((uint64_t)tag << 48);
+            w[u][0] = in ? load_dev(pp) : 0;
+            w[u][1] = in ? load_dev(pp + 1) : 0;
+            w[u][2] = in ? load_dev(pp + 2) : 0;
         }
 #pragma unroll
-        for (int u = 0; u < PU; ++u) {
-            const uint32_t j = j0 + 64u * u + lane;
-            const uint64_t *pp = base + (uint64_t)DSR_PART_WORDS * j * stride;
-            uint32_t spins = 0;
-            while (!(tagged(w[u][0], tag) && tagged(w[u][1], tag) && tagged(w[u][2], tag) && tagged(w[u][3], tag))) {
-                if (++spins > DSR_PARTIAL_SPINS) { ok = false; break; }
-                __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) w[u][q] = load_dev(pp + q);
-            }
-            if (j < cnt) s = add192(s, limbs_value(w[u][0], w[u][1], w[u][2], w[u][3]));
-        }
+        for (int u = 0; u < 8; ++u) s = add192(s, i192{w[u][0], w[u][1], w[u][2]});
     }
     return wave_sum192(s);
 }
 
 /* Last team: the region's reductions from the (group) partials, exact in
  * 192-bit integers, rounded once for fp64. */
-template <int PU>
-__device__ __forceinline__ void combine_teams(const dsr_dregion &R, uint32_t cnt, uint32_t stride, uint32_t lane,
-                                              uint32_t tag, bool &ok)
+__device__ __forceinline__ void combine_teams(const dsr_dregion &R, uint32_t cnt, uint32_t stride, uint32_t lane)
 {
     for (uint32_t r = 0; r < R.n_red; ++r) {
-        const i192 s = sum_partials<PU>(R.partials + (uint64_t)r * R.teams * DSR_PART_WORDS, cnt, stride, lane, tag, ok);
+        const i192 s = sum_partials(R.partials + (uint64_t)r * R.teams * DSR_PART_WORDS, cnt, stride, lane);
         if (lane == 0) {
             R.result->fixed[r][0] = s.w0;
             R.result->fixed[r][1] = s.w1;
@@ -1321,8 +1282,7 @@ __device__ __forceinline__ void publish_record(const dsr_dregion &R, dsr_drec *r
  * reads every partial in one round; with more, the last team of each group
  * first adds up its group's partials and leaves the sum in the group's
  * first partial slot, and the last team overall adds the group sums. */
-template <int PU>
-__device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team, uint32_t lane, uint32_t done0,
+__device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team, uint32_t lane,
                                             uint64_t *done_ts, dsr_drec *rec = nullptr)
 {
     const uint32_t gsize = (R.teams + DSR_ARRIVE_GROUPS - 1) / DSR_ARRIVE_GROUPS;
@@ -1330,8 +1290,7 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team,
     const uint32_t g = team / gsize;
     const uint32_t in_group = min(gsize, R.teams - g * gsize);
     const bool group_sums = R.teams > 512;
-    const uint32_t tag = (done0 + 1) & 0x7FFFu;
-    bool ok = true;
+    drain_memory();                      /* this team's partials are stored */
     uint32_t prev = 0;
     if (lane == 0)
         prev = __hip_atomic_fetch_add(&R.result->group[g * 16], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1342,28 +1301,30 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team,
         if (group_sums) {
             for (uint32_t r = 0; r < R.n_red; ++r) {
                 uint64_t *gp = R.partials + ((uint64_t)r * R.teams + (uint64_t)g * gsize) * DSR_PART_WORDS;
-                const i192 s = sum_partials<PU>(gp, in_group, 1, lane, tag, ok);
-                if (lane == 0) store_partial(gp, s, tag | DSR_TAG_GROUP);
+                const i192 s = sum_partials(gp, in_group, 1, lane);
+                if (lane == 0) {
+                    store_dev(gp, s.w0);
+                    store_dev(gp + 1, s.w1);
+                    store_dev(gp + 2, s.w2);
+                }
             }
+            drain_memory();              /* the group sums are stored */
         }
         if (lane == 0)
             prev = __hip_atomic_fetch_add(&R.result->arrived, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         prev = uniform((uint32_t)__shfl((int)prev, 0, 64));
-        if (prev != ngroups - 1) {
-            if (!ok && lane == 0) atomicCAS(&R.result->error, 0, DSR_E_STATE);
-            return;
-        }
+        if (prev != ngroups - 1) return;
         if (lane == 0) __hip_atomic_store(&R.result->arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (ngroups > 1 && group_sums) combine_teams<PU>(R, ngroups, gsize, lane, tag | DSR_TAG_GROUP, ok);
-    else combine_teams<PU>(R, R.teams, 1, lane, tag, ok);
     int32_t err = 0;
     if (lane == 0) err = __hip_atomic_exchange(&R.result->error, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (ngroups > 1 && group_sums) combine_teams(R, ngroups, gsize, lane);
+    else combine_teams(R, R.teams, 1, lane);
     if (lane < DSR_MAX_LOOPS)
         __hip_atomic_store(&R.result->claim[lane], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (lane == 0) {
-        R.result->final_error = err ? err : (ok ? 0 : DSR_E_STATE);
-        __hip_atomic_store(&R.result->done, done0 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        R.result->final_error = err;
+        R.result->done += 1;
         if (done_ts) *done_ts = wall_clock64();
     }
     if (rec) publish_record(R, rec, lane);
@@ -1513,14 +1474,12 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
                 team_reset(T);
             }
             const dsr_dregion &R = C.serve ? stage_request(T, LP.regions + region) : LP.regions[region];
-            /* launches of this region so far: tags this launch's partials */
-            const uint32_t done0 = uniform(__hip_atomic_load(&R.result->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            run_program<VARIANT>(T, R, C, region, team, (done0 + 1) & 0x7FFFu, barriers, inner_pushes);
+            run_program<VARIANT>(T, R, C, region, team, barriers, inner_pushes);
             uint32_t *tr = (single && C.trace && R.trace) ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
             if (tr && T.lane == 0) tr[87] = (uint32_t)wall_clock64();
             if (C.serve) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); /* outputs out of L2 */
             /* the 1024-thread instance reads fewer partials per round */
-            finish_team<VARIANT < 0 ? 2 : 8>(R, team, T.lane, done0,
+            finish_team(R, team, T.lane,
                                              (LP.done_ts && !LP.published) ? LP.done_ts + region : nullptr,
                                              LP.recs ? LP.recs + region : nullptr);
             if (tr && T.lane == 0) tr[88] = (uint32_t)wall_clock64();
