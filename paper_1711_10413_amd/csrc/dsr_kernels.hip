@@ -262,6 +262,10 @@ struct span_t {
 #ifndef DSR_BALANCE_MIN
 #define DSR_BALANCE_MIN 1
 #endif
+/* fixed chains stream their balanced blocks pipelined across blocks */
+#ifndef DSR_STREAM_BLOCKS
+#define DSR_STREAM_BLOCKS 1
+#endif
 
 template <class F>
 __device__ __forceinline__ void team_blocks(span_t sp, uint32_t lane, lane_acc &A, F &&f)
@@ -417,12 +421,87 @@ __device__ __forceinline__ double uniform_f64(const uint8_t *p)
     return __longlong_as_double((long long)(lo | (hi << 32)));
 }
 
+/* The balanced split for a fixed chain, pipelined across blocks: a block is
+ * one batch (U pairs per lane, 128·U elements); a wave claims its next
+ * block and issues that block's loads before it computes the current one,
+ * so two batches stay in flight however the blocks fall.  A partial last
+ * block of the range goes through fma_span.  Measured 0.2-0.8 us faster
+ * per 2^24-element region than one fma_span per claimed block for up to 32
+ * scalars, 0.8 us slower for 64 (whose batches are half as long), which
+ * keeps the per-block spans. */
+template <int NI, int NF>
+__device__ __forceinline__ void fma_blocks(const double (&s)[NI + NF], const GLB float *__restrict__ x,
+                                           GLB double *__restrict__ y, span_t sp, uint32_t lane, lane_acc &A)
+{
+    constexpr int U = (NI + NF >= 64) ? 4 : (NI + NF <= 4 ? DSR_FIXED_U_LIGHT : 8);
+    constexpr uint32_t BLK = 128u * U;
+    LDSQ uint32_t *ctr = (LDSQ uint32_t *)(dsr_lds + offsetof(cb_header, blocks));
+    const uint64_t lo = sp.lo;
+    const uint32_t nfull = sp.hi > lo ? (uint32_t)((sp.hi - lo) / BLK) : 0u;
+    const bool tail = sp.hi > lo + (uint64_t)nfull * BLK;
+    const GLB f32x2 *__restrict__ x2 = (const GLB f32x2 *)x;
+    GLB f64x2 *__restrict__ y2 = (GLB f64x2 *)y;
+    lane_acc Ac[2] = {acc_zero(), acc_zero()};
+    uint32_t c = 0;
+    if (lane == 0) c = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    c = uniform((uint32_t)__shfl((int)c, 0, 64));
+    f32x2 cur[U];
+    if (c < nfull) {
+        const uint64_t v = (lo >> 1) + (uint64_t)c * (BLK / 2) + lane;
+#pragma unroll
+        for (int u = 0; u < U; ++u) cur[u] = __builtin_nontemporal_load(&x2[v + 64u * u]);
+    }
+    uint32_t since = 0;
+    while (c < nfull) {
+        uint32_t cn = 0;
+        if (lane == 0) cn = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        cn = uniform((uint32_t)__shfl((int)cn, 0, 64));
+        f32x2 nxt[U];
+        if (cn < nfull) {
+            const uint64_t vn = (lo >> 1) + (uint64_t)cn * (BLK / 2) + lane;
+#pragma unroll
+            for (int u = 0; u < U; ++u) nxt[u] = __builtin_nontemporal_load(&x2[vn + 64u * u]);
+        }
+        const uint64_t v = (lo >> 1) + (uint64_t)c * (BLK / 2) + lane;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            f64x2 r;
+            r.x = chain<NI, NF>(s, (double)cur[u].x);
+            r.y = chain<NI, NF>(s, (double)cur[u].y);
+            __builtin_nontemporal_store(r, &y2[v + 64u * u]);
+            acc_add_f64(Ac[0], r.x);
+            acc_add_f64(Ac[1], r.y);
+        }
+        /* a block adds U values to each of the two bins: flush well before 2^16 */
+        if (++since == 2048) {
+            acc_merge(A, Ac[0]);
+            acc_merge(A, Ac[1]);
+            Ac[0] = acc_zero();
+            Ac[1] = acc_zero();
+            acc_flush(A);
+            since = 0;
+        }
+        c = cn;
+#pragma unroll
+        for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+    }
+    acc_merge(A, Ac[0]);
+    acc_merge(A, Ac[1]);
+    /* the claim that went past the full blocks takes the partial block */
+    if (c == nfull && tail) fma_span<NI, NF>(s, x, y, span_t{lo + (uint64_t)nfull * BLK, sp.hi, lane, 64u}, A);
+}
+
 template <int NI, int NF>
 __device__ __forceinline__ void fma_fixed_spans(const double (&s)[NI + NF], const dsr_dloop &L, span_t sp,
                                                 lane_acc &A, uint32_t *claim, uint32_t lane)
 {
     const GLB float *x = (const GLB float *)L.in;
     GLB double *y = (GLB double *)L.out;
+    /* (a team range starting on an odd element keeps the per-span path) */
+    if (DSR_STREAM_BLOCKS && NI + NF < 64 && L.schedule == DSR_SCHED_STATIC && !(uniform((uint32_t)sp.lo) & 1u)) {
+        fma_blocks<NI, NF>(s, x, y, sp, lane, A);
+        return;
+    }
     for_spans(L, sp, lane, claim, A, [&](span_t q) { fma_span<NI, NF>(s, x, y, q, A); }, NI + NF >= DSR_BALANCE_MIN);
 }
 

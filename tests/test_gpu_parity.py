@@ -351,6 +351,23 @@ def test_cross_team_combine_team_counts(teams):
     D.dsr_destroy(ctx)
 
 
+@pytest.mark.parametrize("K,chunk,teams", [(8, 10001, 4), (1, 1025, 7), (64, 4099, 3), (16, 2048, 5)])
+def test_fixed_chain_user_chunks(K, chunk, teams):
+    """Caller-chosen team chunks: odd team starts, chunks that are and are
+    not whole numbers of streaming blocks."""
+    say("user chunk", K, chunk, teams)
+    n = chunk * teams - 17
+    cf, x_np = W.cfg2_inputs(K, n=n)
+    ctx = D.dsr_init(wg_size=256, lds_slab_bytes=4096, max_teams=64)
+    x = torch.from_numpy(x_np).cuda()
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, r = fma_region(ctx, teams, cf.s_i32, cf.s_f64, x, y, chunk=chunk)
+    assert st == 0
+    check_fma(r, x_np, cf.s_i32, cf.s_f64, y)
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+
+
 def test_fma_wide_workgroup_and_empty():
     say("fma wg 1024, n 0")
     cf, x_np = W.cfg2_inputs(8, n=100003)
