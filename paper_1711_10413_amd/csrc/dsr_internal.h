@@ -130,10 +130,20 @@ struct dsr_dconfig {
     uint32_t pad;
 };
 
+/* Compiled instances of the region kernel: (tag, largest workgroup, variant).
+ * The build compiles dsr_kernels.hip once per entry, in parallel, and
+ * dsr_dispatch.cpp routes each launch to one of them. */
+#define DSR_INSTANCES(X) \
+    X(256_0, 256, 0)     \
+    X(256_1, 256, 1)     \
+    X(256_2, 256, 2)     \
+    X(512_0, 512, 0)     \
+    X(1024_m1, 1024, -1)
+
 #ifdef __cplusplus
 extern "C" {
 #endif
-/* Kernel launchers (dsr_kernels.hip). Return hipError_t as int. */
+/* Kernel launchers (dsr_dispatch.cpp). Return hipError_t as int. */
 int dsr_launch_region_kernel(const dsr_dlaunch *lp, const dsr_dconfig *cfg, uint32_t grid,
                              uint32_t wg_size, uint32_t lds_bytes, uint32_t variant,
                              void *stream);

@@ -1596,73 +1596,46 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
     }
 }
 
-template <int MAXWG, int VARIANT>
-static hipError_t launch_variant(const dsr_dlaunch *lp, const dsr_dconfig *cfg, uint32_t grid,
-                                 uint32_t wg_size, uint32_t lds_bytes, hipStream_t s)
+/* ---- this object's instance --------------------------------------------
+ * The build compiles this file once per kernel instance, in parallel, with
+ * DSR_INST_MAXWG, DSR_INST_VARIANT and DSR_INST_TAG defined; each object
+ * exports its instance's launcher, occupancy and register queries under
+ * names carrying the tag, and dsr_dispatch.cpp picks among them. */
+#if !defined(DSR_INST_MAXWG) || !defined(DSR_INST_VARIANT) || !defined(DSR_INST_TAG)
+#error "compile with -DDSR_INST_MAXWG=<threads> -DDSR_INST_VARIANT=<v> -DDSR_INST_TAG=<tag>"
+#endif
+#define DSR_INST_CAT2(a, b) a##b
+#define DSR_INST_CAT(a, b) DSR_INST_CAT2(a, b)
+#define DSR_INST_KERNEL dsr_region_kernel<DSR_INST_MAXWG, DSR_INST_VARIANT>
+
+extern "C" int DSR_INST_CAT(dsr_inst_launch_, DSR_INST_TAG)(const dsr_dlaunch *lp, const dsr_dconfig *cfg,
+                                                            uint32_t grid, uint32_t wg_size, uint32_t lds_bytes,
+                                                            void *stream)
 {
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void *)dsr_region_kernel<MAXWG, VARIANT>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute((const void *)DSR_INST_KERNEL, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL((dsr_region_kernel<MAXWG, VARIANT>), dim3(grid), dim3(wg_size), lds_bytes, s,
-                       *lp, *cfg);
-    return hipGetLastError();
+    hipLaunchKernelGGL(DSR_INST_KERNEL, dim3(grid), dim3(wg_size), lds_bytes, (hipStream_t)stream, *lp, *cfg);
+    return (int)hipGetLastError();
 }
 
-extern "C" int dsr_launch_region_kernel(const dsr_dlaunch *lp, const dsr_dconfig *cfg, uint32_t grid,
-                                        uint32_t wg_size, uint32_t lds_bytes, uint32_t variant,
-                                        void *stream)
+extern "C" int DSR_INST_CAT(dsr_inst_occupancy_, DSR_INST_TAG)(uint32_t wg_size, uint32_t lds_bytes)
 {
-    hipStream_t s = (hipStream_t)stream;
-    if (wg_size > 512) return (int)launch_variant<1024, -1>(lp, cfg, grid, wg_size, lds_bytes, s);
-    if (wg_size > 256) return (int)launch_variant<512, 0>(lp, cfg, grid, wg_size, lds_bytes, s);
-    switch (variant) {
-    case 0: return (int)launch_variant<256, 0>(lp, cfg, grid, wg_size, lds_bytes, s);
-    case 1: return (int)launch_variant<256, 1>(lp, cfg, grid, wg_size, lds_bytes, s);
-    default: return (int)launch_variant<256, 2>(lp, cfg, grid, wg_size, lds_bytes, s);
-    }
-}
-
-template <int MAXWG, int VARIANT>
-static int occupancy_of(uint32_t wg_size, uint32_t lds_bytes)
-{
-    (void)hipFuncSetAttribute((const void *)dsr_region_kernel<MAXWG, VARIANT>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void *)DSR_INST_KERNEL, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)dsr_region_kernel<MAXWG, VARIANT>,
-                                                     (int)wg_size, lds_bytes) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)DSR_INST_KERNEL, (int)wg_size, lds_bytes) !=
+        hipSuccess)
         return 0;
     return n;
 }
 
-extern "C" int dsr_region_kernel_occupancy(uint32_t wg_size, uint32_t lds_bytes, uint32_t variant)
-{
-    if (wg_size > 512) return occupancy_of<1024, -1>(wg_size, lds_bytes);
-    if (wg_size > 256) return occupancy_of<512, 0>(wg_size, lds_bytes);
-    switch (variant) {
-    case 0: return occupancy_of<256, 0>(wg_size, lds_bytes);
-    case 1: return occupancy_of<256, 1>(wg_size, lds_bytes);
-    default: return occupancy_of<256, 2>(wg_size, lds_bytes);
-    }
-}
-
-template <int MAXWG, int VARIANT>
-static int regs_of()
+extern "C" int DSR_INST_CAT(dsr_inst_regs_, DSR_INST_TAG)(void)
 {
     hipFuncAttributes a{};
-    if (hipFuncGetAttributes(&a, (const void *)dsr_region_kernel<MAXWG, VARIANT>) != hipSuccess) return 0;
+    if (hipFuncGetAttributes(&a, (const void *)DSR_INST_KERNEL) != hipSuccess) return 0;
     return a.numRegs;
-}
-
-extern "C" int dsr_region_kernel_regs(uint32_t wg_size, uint32_t variant)
-{
-    if (wg_size > 512) return regs_of<1024, -1>();
-    if (wg_size > 256) return regs_of<512, 0>();
-    switch (variant) {
-    case 0: return regs_of<256, 0>();
-    case 1: return regs_of<256, 1>();
-    default: return regs_of<256, 2>();
-    }
 }
