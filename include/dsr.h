@@ -166,11 +166,19 @@ typedef struct dsr_region dsr_region;
 int dsr_init(dsr_ctx **out, const dsr_config *cfg, int device);
 int dsr_destroy(dsr_ctx *ctx);
 
-/* Start building a region that runs on `teams` teams (1 .. cfg.max_teams). */
+/* Start building a generic-mode target region that runs on `teams` teams
+ * (1 .. cfg.max_teams).  Each team is its own contention group: one master
+ * runs the sequential code while its workers wait to be handed parallel
+ * work (section 4, Figure 2).  *out receives the region's program, empty;
+ * the caller owns it until dsr_region_free.  DSR_E_INVAL for a bad team
+ * count or NULL arguments. */
 int dsr_region_begin(dsr_ctx *ctx, int32_t teams, dsr_region **out);
 
 /* Master code block: push a frame of `nbytes` declared bytes (rounded up to
- * 16 on the stack).  The frame's first `init_bytes` bytes are copied from
+ * 16 on the stack).  This is the allocation of the master's implicitly
+ * shared locals on the per-team shared-memory stack that replaces the
+ * local depot (section 5.3.1), with the global-memory fallback of section
+ * 5.2 taken on the device when the frame does not fit.  The frame's first `init_bytes` bytes are copied from
  * the host buffer `init` (copied at this call; NULL if init_bytes == 0) and
  * the rest is zero.  If `init_stride` is nonzero, team t copies from
  * init + t*init_stride instead (the buffer then holds teams*init_stride
@@ -215,12 +223,17 @@ int dsr_publish_list(dsr_region *r, const dsr_ref *refs, int32_t n, int32_t body
  * reduction slots and nested-level sub-stacks); 0 for a bad size. */
 uint32_t dsr_control_bytes(uint32_t wg_size);
 
-/* Pop frame `frame`; it must be the most recently pushed live frame.
- * DSR_E_UNDERFLOW on an empty stack, DSR_E_ORDER if not the top. */
+/* Pop frame `frame`; it must be the most recently pushed live frame (the
+ * shared stack of section 5.3.1 is released in LIFO order when the
+ * master's locals go out of scope).  DSR_E_UNDERFLOW on an empty stack,
+ * DSR_E_ORDER if not the top, DSR_E_STATE if `frame` is not live. */
 int dsr_pop(dsr_region *r, int32_t frame);
 
 /* Validate the program (DSR_E_LIVE if a frame is still live) and launch it
- * as one kernel of `teams` workgroups on `stream` (hipStream_t as void*).
+ * as one kernel of `teams` workgroups on `stream` (hipStream_t as void*):
+ * the generic-mode kernel of section 4 (Figure 2: team init, the master's
+ * sequential code with its forks and joins, the workers' loop of Figure 3,
+ * terminate).
  * Asynchronous: results are available after dsr_region_sync.  A region may
  * be launched again (the same program over the same buffers) after its
  * previous launch, e.g. next on the same stream.  The stream must stay
@@ -270,6 +283,8 @@ int dsr_region_elapsed(dsr_region *r, float *ms);
 int dsr_region_free(dsr_region *r);
 
 /* ---- batched form ---------------------------------------------------------
+ * Not in the paper: the batched workload (10,000 region instances in one
+ * persistent, graph-captured launch) built on the paper's runtime.
  * Many regions run in one persistent launch: workgroups stay resident and
  * their master waves claim (region, team) items from a device counter,
  * largest per-team work first, running each region's program as that team;
@@ -330,7 +345,7 @@ int dsr_batch_elapsed(dsr_batch *b, float *ms);
 
 int dsr_batch_free(dsr_batch *b);
 
-/* Autotuner: time `reps` persistent launches of the batch under each of
+/* Autotuner (not in the paper): time `reps` persistent launches of the batch under each of
  * the `n_cand` candidate tunes (candidates that do not fit the device are
  * skipped), leave the fastest in effect, and return it in *best and every
  * candidate's mean milliseconds in ms[i] (negative if skipped). */
@@ -338,6 +353,8 @@ int dsr_autotune(dsr_batch *b, const dsr_tune *cand, int32_t n_cand, int32_t rep
                  dsr_tune *best, float *ms);
 
 /* ---- served form ----------------------------------------------------------
+ * Not in the paper: the served workload (Poisson-arriving region requests
+ * with admission by LDS and HBM budget) built on the paper's runtime.
  * A resident server kernel runs region requests as they arrive.  The host
  * submits a request (a finished region used as a program template) into a
  * free slot: its program, loop descriptors and frame images are copied into
@@ -354,10 +371,14 @@ int dsr_autotune(dsr_batch *b, const dsr_tune *cand, int32_t n_cand, int32_t rep
  * requests' team stacks would exceed the server's budget (the resident
  * teams' LDS slabs and HBM slots).  Budgets are returned on completion.
  *
- * The server kernel leaves when dsr_serve_stop is called, or by itself
- * after `idle_ms` without new work; from then on dsr_serve_submit fails
- * with DSR_E_STATE.  A device-wide synchronisation (hipDeviceSynchronize)
- * waits for the resident server kernel, i.e. until it leaves. */
+ * The server closes when dsr_serve_stop is called, or by itself once no
+ * request has been published for `idle_ms` (one decision for the whole
+ * server, on the device clock).  Closing is all-or-none: every request
+ * published before the close completes, and a submit that races the close
+ * either runs or fails with DSR_E_STATE and takes its request back; after
+ * the close every submit fails with DSR_E_STATE.  A device-wide
+ * synchronisation (hipDeviceSynchronize) waits for the resident server
+ * kernel, i.e. until it has closed and drained. */
 typedef struct dsr_server dsr_server;
 
 typedef struct dsr_serve_cfg {
@@ -382,13 +403,14 @@ typedef struct dsr_done {
                                  device clock since the server started           */
 } dsr_done;
 
-/* Launch the server kernel on its own stream.  Regions submitted later must
+/* Launch the server kernel on its own stream (not in the paper).  Regions submitted later must
  * belong to `ctx` and use one of the bodies compiled into the server (all
  * bodies; fixed-length fma chains up to 8+8 scalars, longer ones through the
  * run-time loop). */
 int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_server **out);
 
-/* Submit region `program` (not launched itself; its frames all popped).
+/* Submit region `program` (not launched itself; its frames all popped) (not
+ * in the paper).
  * `outs` (may be NULL) replaces the output pointer of each of its loops,
  * so one template can serve many requests with separate output buffers.
  * *ticket identifies the request in dsr_serve_poll.  The server runs on a
@@ -427,9 +449,29 @@ int dsr_serve_replay(dsr_server *s, dsr_region *const *programs, const int32_t *
 int dsr_batch_replay_serial(dsr_batch *b, const int32_t *prog, const double *arrival_s, int32_t n,
                             double *latency_us);
 
-/* Stop the server: the kernel drains the published items and exits; then
- * frees the server.  Completed requests not yet polled are dropped. */
+/* Stop the server: the kernel runs every request published before the stop
+ * and exits; then frees the server.  Completed requests not yet polled are
+ * dropped. */
 int dsr_serve_stop(dsr_server *s);
+
+/* State of a server, for monitoring: its grid, how many of its workgroups
+ * have started and left, whether it has closed (stop or idle) and how many
+ * items it serves in all once closed, the items published so far and the
+ * requests not yet collected.  A grid that never fully starts means the
+ * device holds fewer of the server's workgroups at once than the occupancy
+ * query promised; the server stays correct (no workgroup waits for
+ * another) but serves with fewer teams. */
+typedef struct dsr_serve_stat {
+    uint32_t grid;
+    uint32_t started;
+    uint32_t exited;
+    uint32_t closed;
+    uint32_t final_items;
+    uint32_t published;
+    uint32_t in_flight;
+    uint32_t pad;
+} dsr_serve_stat;
+int dsr_serve_status(dsr_server *s, dsr_serve_stat *out);
 
 /* ---- footprint and occupancy model ------------------------------------------
  * How many teams a compute unit holds at once, and what limits it, from

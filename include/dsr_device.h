@@ -23,7 +23,8 @@
  * wave with uniform arguments; only lane 0 writes the shared state.
  *
  * A frame is a value {space, offset, size}, never a raw pointer: bodies
- * turn it into an LDS or HBM address with frame_lds / frame_hbm.
+ * reach a shared variable in it with slot<V>(team, frame, offset), or take
+ * the frame's base with frame_lds / frame_hbm.
  *
  * LDS layout of a team (dynamic shared memory):
  *   [header 64 B][frame table 16 x 16 B][reference list 20 x 8 B]
@@ -253,6 +254,16 @@ __device__ inline void end_parallel(team_t &T, uint64_t w0, uint64_t w1, uint64_
 /* Frame address in LDS or in the team's HBM slot. */
 __device__ inline uint8_t *frame_lds(const team_t &T, frame_t f) { return T.stack_lds + f.off; }
 __device__ inline uint8_t *frame_hbm(const team_t &T, frame_t f) { return T.stack_hbm + f.off; }
+
+/* Typed address of the shared variable `off` bytes into frame f, in
+ * whichever space the frame lives (section 5.1: workers reach the master's
+ * locals through the reference they are handed, not by copy).  `off` must
+ * be a multiple of alignof(V) and off + sizeof(V) <= f.size. */
+template <class V>
+__device__ inline V *slot(const team_t &T, frame_t f, uint32_t off)
+{
+    return (V *)((f.space == SPACE_LDS ? T.stack_lds : T.stack_hbm) + f.off + off);
+}
 
 } // namespace dsr
 

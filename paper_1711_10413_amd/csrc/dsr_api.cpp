@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
+#include <chrono>
 #include <new>
 #include <vector>
 
@@ -1019,7 +1020,10 @@ struct dsr_server {
     uint8_t *h_block;                 /* host-coherent control block         */
     uint32_t *published;
     uint32_t *stop;
-    uint32_t *exited;
+    uint32_t *closing;                /* device: the server is closing        */
+    uint32_t *final_items;            /* device: 1 + items served (0 = open)  */
+    uint32_t *wg_started;             /* per resident workgroup               */
+    uint32_t *wg_exited;
     uint64_t *start_ticks;
     uint32_t *items;
     dsr_dregion *regs;
@@ -1087,9 +1091,11 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
     S->lds_used = S->hbm_used = 0;
     S->lds_budget = (uint64_t)grid * t.lds_slab_bytes * c.budget_pct / 100;
     S->hbm_budget = (uint64_t)grid * ctx->cfg.hbm_slab_bytes * c.budget_pct / 100;
-    /* host-coherent control block: published, stop, start ticks, item ring,
-     * region descriptors, completion records */
-    const size_t o_items = 256, o_regs = o_items + align256((size_t)c.ring_items * 8);
+    /* host-coherent control block: published, stop, start ticks, closing,
+     * final count, per-workgroup start and exit flags, item ring, region
+     * descriptors, completion records */
+    const size_t o_wg = 512, o_items = o_wg + 2 * align256((size_t)grid * 4);
+    const size_t o_regs = o_items + align256((size_t)c.ring_items * 8);
     const size_t o_recs = o_regs + align256((size_t)c.slots * sizeof(dsr_dregion));
     const size_t blk = o_recs + align256((size_t)c.slots * sizeof(dsr_drec));
     const size_t slot_h = align256(DSR_SERVE_MAX_OPS * sizeof(dsr_op)) +
@@ -1108,8 +1114,9 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
         delete S;
         return DSR_E_NOMEM;
     }
-    if (hipMalloc((void **)&S->d_arena, slot_d * c.slots + 256) != hipSuccess ||
-        hipMemset(S->d_arena, 0, slot_d * c.slots + 256) != hipSuccess) {
+    const size_t ctl_d = DSR_SRV_WORDS * sizeof(uint32_t);
+    if (hipMalloc((void **)&S->d_arena, slot_d * c.slots + ctl_d) != hipSuccess ||
+        hipMemset(S->d_arena, 0, slot_d * c.slots + ctl_d) != hipSuccess) {
         (void)hipHostFree(S->h_arena);
         (void)hipHostFree(S->h_block);
         delete S;
@@ -1118,7 +1125,10 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
     S->published = (uint32_t *)S->h_block;
     S->stop = (uint32_t *)(S->h_block + 64);
     S->start_ticks = (uint64_t *)(S->h_block + 128);
-    S->exited = (uint32_t *)(S->h_block + 192);
+    S->closing = (uint32_t *)(S->h_block + 192);
+    S->final_items = (uint32_t *)(S->h_block + 256);
+    S->wg_started = (uint32_t *)(S->h_block + o_wg);
+    S->wg_exited = (uint32_t *)(S->h_block + o_wg + align256((size_t)grid * 4));
     S->items = (uint32_t *)(S->h_block + o_items);
     S->regs = (dsr_dregion *)(S->h_block + o_regs);
     S->recs = (dsr_drec *)(S->h_block + o_recs);
@@ -1154,7 +1164,10 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
     LP.recs = S->recs;
     LP.ring_mask = c.ring_items - 1;
     LP.idle_limit = (uint64_t)c.idle_ms * 100000ull;
-    LP.exited = S->exited;
+    LP.closing = S->closing;
+    LP.final_items = S->final_items;
+    LP.wg_started = S->wg_started;
+    LP.wg_exited = S->wg_exited;
     dsr_dconfig C = make_dconfig(ctx, t.wg_size, t.lds_slab_bytes, t.overflow_threshold, t.master_joins, 0);
     C.serve = 1;
     if (dsr_launch_region_kernel(&LP, &C, grid, t.wg_size, S->lds_bytes, variant, S->stream) != 0) {
@@ -1169,13 +1182,24 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
     return DSR_OK;
 }
 
+/* Return slot k and its admission budget. */
+static void serve_release(dsr_server *S, uint32_t k)
+{
+    serve_slot &sl = S->slots[k];
+    sl.busy = false;
+    S->lds_used -= sl.lds_cost;
+    S->hbm_used -= sl.hbm_cost;
+    S->in_flight--;
+    S->free_slots.push_back(k);
+}
+
 extern "C" int dsr_serve_submit(dsr_server *S, dsr_region *r, void *const *outs, int32_t n_outs,
                                 uint64_t *ticket)
 {
     if (!S || !r || !ticket || n_outs < 0) return DSR_E_INVAL;
     if (r->ctx != S->ctx) return DSR_E_INVAL;
-    /* a workgroup that left (idle timeout) means the server is going away */
-    if (__atomic_load_n(S->exited, __ATOMIC_ACQUIRE) != 0) return DSR_E_STATE;
+    /* the server closed (stop, or no new work for idle_ms) */
+    if (__atomic_load_n(S->closing, __ATOMIC_SEQ_CST) != 0) return DSR_E_STATE;
     if (!r->live.empty()) return DSR_E_LIVE;
     if (r->ops.size() > DSR_SERVE_MAX_OPS || r->loops.size() > DSR_SERVE_MAX_LOOPS) return DSR_E_INVAL;
     if ((uint32_t)r->teams > S->cfg.max_teams || r->init.size() > S->cfg.slot_bytes) return DSR_E_INVAL;
@@ -1235,8 +1259,25 @@ extern "C" int dsr_serve_submit(dsr_server *S, dsr_region *r, void *const *outs,
     S->hbm_used += hcost;
     S->in_flight++;
     S->pub += (uint32_t)r->teams;
-    /* everything above is visible before the new count */
-    __atomic_store_n(S->published, S->pub, __ATOMIC_RELEASE);
+    /* everything above is visible before the new count; then look for a
+     * close the device may have begun meanwhile (its side writes the
+     * closing flag, then reads the count: one of the two reads sees the
+     * other side's write) */
+    __atomic_store_n(S->published, S->pub, __ATOMIC_SEQ_CST);
+    __atomic_thread_fence(__ATOMIC_SEQ_CST);
+    if (__atomic_load_n(S->closing, __ATOMIC_SEQ_CST) != 0) {
+        /* the closing workgroup reports the count it read right away */
+        uint32_t fin = 0;
+        const auto t0 = std::chrono::steady_clock::now();
+        while ((fin = __atomic_load_n(S->final_items, __ATOMIC_ACQUIRE)) == 0) {
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(10)) return DSR_E_HIP;
+        }
+        if ((int32_t)(S->pub - (fin - 1u)) > 0) {
+            /* published after the close: the device will not run it */
+            serve_release(S, k);
+            return DSR_E_STATE;
+        }
+    }
     *ticket = tk;
     return DSR_OK;
 }
@@ -1263,11 +1304,7 @@ extern "C" int dsr_serve_poll(dsr_server *S, dsr_done *out, int32_t max)
         }
         const uint64_t t0 = __atomic_load_n(S->start_ticks, __ATOMIC_ACQUIRE);
         d.device_us = ((double)rec.ticks - (double)t0) / 100.0;
-        sl.busy = false;
-        S->lds_used -= sl.lds_cost;
-        S->hbm_used -= sl.hbm_cost;
-        S->in_flight--;
-        S->free_slots.push_back(k);
+        serve_release(S, k);
     }
     return n;
 }
@@ -1276,6 +1313,24 @@ extern "C" int dsr_serve_pending(dsr_server *S)
 {
     if (!S) return DSR_E_INVAL;
     return (int)S->in_flight;
+}
+
+extern "C" int dsr_serve_status(dsr_server *S, dsr_serve_stat *out)
+{
+    if (!S || !out) return DSR_E_INVAL;
+    dsr_serve_stat st{};
+    st.grid = S->grid;
+    for (uint32_t b = 0; b < S->grid; ++b) {
+        st.started += __atomic_load_n(S->wg_started + b, __ATOMIC_ACQUIRE) != 0;
+        st.exited += __atomic_load_n(S->wg_exited + b, __ATOMIC_ACQUIRE) != 0;
+    }
+    st.closed = __atomic_load_n(S->closing, __ATOMIC_ACQUIRE) != 0;
+    const uint32_t fin = __atomic_load_n(S->final_items, __ATOMIC_ACQUIRE);
+    st.final_items = fin ? fin - 1 : 0;
+    st.published = S->pub;
+    st.in_flight = S->in_flight;
+    *out = st;
+    return DSR_OK;
 }
 
 extern "C" int dsr_serve_stop(dsr_server *S)

@@ -101,20 +101,36 @@ struct dsr_dlaunch {
     uint32_t n_items;
     uint32_t n_regions;
     uint32_t *counter;      /* [0] next item, [1] workgroups finished;
-                               served form: [16] device copy of the published
-                               count, [32] device copy of the stop flag */
+                               served form, see DSR_SRV_* below */
     uint64_t *done_ts;      /* per region: wall clock when its result was written;
                                [n_regions]: when item 0 was claimed */
     /* served form (published != null): items arrive over time in a ring */
     const uint32_t *published; /* host-coherent: items published so far   */
-    const uint32_t *stop;      /* host-coherent: nonzero = drain and exit  */
+    const uint32_t *stop;      /* host-coherent: nonzero = close the server */
     dsr_drec *recs;            /* host-coherent completion records, per slot */
     uint32_t ring_mask;        /* ring capacity - 1 (power of two)          */
     uint32_t pad2;
-    uint32_t *exited;          /* host-coherent: workgroups that have left   */
+    uint32_t *closing;         /* host-coherent: set by the device when it
+                                  starts to close the server                */
+    uint32_t *final_items;     /* host-coherent: 1 + the published count the
+                                  device serves before it leaves (0 = open)  */
+    uint32_t *wg_started;      /* host-coherent, per workgroup: 1 once it runs */
+    uint32_t *wg_exited;       /* host-coherent, per workgroup: 1 once it left */
     uint64_t *start_ts;        /* if set, block 0 stamps its start time here */
-    uint64_t idle_limit;       /* exit after this many ticks with no new item */
+    uint64_t idle_limit;       /* close after this many ticks in which the
+                                  published count did not change            */
 };
+
+/* Served form: control words in device memory (LP.counter, 32-bit words).
+ * The claim counter, the device copy of the host's published count, the
+ * server state, the item count it serves before leaving, and the wall
+ * clock of the last change of the published count (64-bit, two words). */
+#define DSR_SRV_CLAIM 0
+#define DSR_SRV_PUB 16
+#define DSR_SRV_STATE 32      /* 0 open, 1 closing, 2 closed            */
+#define DSR_SRV_FINAL 48      /* valid once the state is 2              */
+#define DSR_SRV_LAST 64       /* uint64 at counter + 64                 */
+#define DSR_SRV_WORDS 128
 
 /* Launch-wide configuration. */
 struct dsr_dconfig {

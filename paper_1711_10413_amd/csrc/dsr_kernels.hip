@@ -506,14 +506,16 @@ __device__ __forceinline__ void fma_fixed_spans(const double (&s)[NI + NF], cons
 }
 
 template <int NI, int NF>
-__device__ __forceinline__ void body_fma_fixed(const uint8_t *fb, const dsr_dloop &L, span_t sp,
+__device__ __forceinline__ void body_fma_fixed(const team_t &T, frame_t f, const dsr_dloop &L, span_t sp,
                                                lane_acc &A, uint32_t *claim, uint32_t lane)
 {
+    /* frame layout: [24 B exact sum][NF fp64][NI int32] */
     double s[NI + NF];
 #pragma unroll
-    for (int k = 0; k < NI; ++k) s[k] = (double)(int32_t)uniform_u32(fb + 24 + 8 * NF + 4 * k);
+    for (int k = 0; k < NI; ++k)
+        s[k] = (double)(int32_t)uniform_u32((const uint8_t *)slot<int32_t>(T, f, 24 + 8 * NF + 4 * k));
 #pragma unroll
-    for (int k = 0; k < NF; ++k) s[NI + k] = uniform_f64(fb + 24 + 8 * k);
+    for (int k = 0; k < NF; ++k) s[NI + k] = uniform_f64((const uint8_t *)slot<double>(T, f, 24 + 8 * k));
     fma_fixed_spans<NI, NF>(s, L, sp, A, claim, lane);
 }
 
@@ -864,11 +866,15 @@ __device__ __forceinline__ void body_gather_nested(team_t &T, AP arr, frame_t ou
 }
 
 /* Cross-team traffic (partials, arrival counters, results) uses
- * device-scope relaxed atomics: on gfx950 these bypass the per-XCD L2,
- * which is not coherent across XCDs, so no L2 write-back or invalidate
- * (what a device-scope fence costs) is needed.  Ordering between a team's
- * partial and its arrival is enforced by waiting for the partial's store
- * to complete before the arrival atomic is issued. */
+ * device-scope relaxed atomics: on gfx950 these are performed at the
+ * device's coherence point, past the per-XCD L2 (which is not coherent
+ * across XCDs), so a team's partial needs no L2 write-back (what a
+ * device-scope release costs every team).  The hardware assumption this
+ * rests on: a team waits for its partial's stores to complete (s_waitcnt)
+ * before issuing its arrival atomic, and a store to the coherence point
+ * that has completed is seen by any later device-scope read.  The last
+ * arriver of a group and of the region takes a device-scope acquire
+ * before reading the partials, once per group. */
 __device__ __forceinline__ void store_dev(uint64_t *p, uint64_t v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -903,26 +909,27 @@ __device__ __forceinline__ void run_body(team_t &T, uint32_t body, frame_t f, co
     const uint32_t lane = T.lane;
     switch (body) {
     case DSR_BODY_AFFINE_XOR: {
-        const uint8_t *fr = frame_ptr(T, f) + 8;
-        const uint32_t a = uniform_u32(fr), b = uniform_u32(fr + 4);
-        const uint32_t c = uniform_u32(fr + 8), d = uniform_u32(fr + 12);
+        /* frame layout: [8 B int64 sum][a][b][c][d] */
+        const uint32_t a = uniform_u32((const uint8_t *)slot<int32_t>(T, f, 8));
+        const uint32_t b = uniform_u32((const uint8_t *)slot<int32_t>(T, f, 12));
+        const uint32_t c = uniform_u32((const uint8_t *)slot<int32_t>(T, f, 16));
+        const uint32_t d = uniform_u32((const uint8_t *)slot<int32_t>(T, f, 20));
         GLB int32_t *out = (GLB int32_t *)L.out;
         for_spans(L, sp, lane, claim, A, [&](span_t q) { affine_span(a, b, c, d, out, q, A); });
         break;
     }
     case DSR_BODY_FMA_CHAIN: {
-        const uint8_t *fb = frame_ptr(T, f);
         const uint32_t ni = L.ni, nf = L.nf;
         if (VARIANT >= 0 && L.alen == 0) {
-            if (ni == 1 && nf == 0) { body_fma_fixed<1, 0>(fb, L, sp, A, claim, lane); break; }
-            if (ni == 1 && nf == 1) { body_fma_fixed<1, 1>(fb, L, sp, A, claim, lane); break; }
-            if (ni == 2 && nf == 2) { body_fma_fixed<2, 2>(fb, L, sp, A, claim, lane); break; }
-            if (ni == 4 && nf == 4) { body_fma_fixed<4, 4>(fb, L, sp, A, claim, lane); break; }
-            if (ni == 8 && nf == 8) { body_fma_fixed<8, 8>(fb, L, sp, A, claim, lane); break; }
+            if (ni == 1 && nf == 0) { body_fma_fixed<1, 0>(T, f, L, sp, A, claim, lane); break; }
+            if (ni == 1 && nf == 1) { body_fma_fixed<1, 1>(T, f, L, sp, A, claim, lane); break; }
+            if (ni == 2 && nf == 2) { body_fma_fixed<2, 2>(T, f, L, sp, A, claim, lane); break; }
+            if (ni == 4 && nf == 4) { body_fma_fixed<4, 4>(T, f, L, sp, A, claim, lane); break; }
+            if (ni == 8 && nf == 8) { body_fma_fixed<8, 8>(T, f, L, sp, A, claim, lane); break; }
             if constexpr (VARIANT >= 1)
-                if (ni == 16 && nf == 16) { body_fma_fixed<16, 16>(fb, L, sp, A, claim, lane); break; }
+                if (ni == 16 && nf == 16) { body_fma_fixed<16, 16>(T, f, L, sp, A, claim, lane); break; }
             if constexpr (VARIANT >= 2)
-                if (ni == 32 && nf == 32) { body_fma_fixed<32, 32>(fb, L, sp, A, claim, lane); break; }
+                if (ni == 32 && nf == 32) { body_fma_fixed<32, 32>(T, f, L, sp, A, claim, lane); break; }
         }
         /* run-time chain (the host admits at most 64 scalars); workgroups
          * above 512 threads have 128 registers per lane */
@@ -1375,6 +1382,8 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team,
         prev = __hip_atomic_fetch_add(&R.result->group[g * 16], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     prev = uniform((uint32_t)__shfl((int)prev, 0, 64));
     if (prev != in_group - 1) return;
+    /* the last arriver of a group reads the others' partials: acquire */
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (lane == 0) __hip_atomic_store(&R.result->group[g * 16], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (ngroups > 1) {
         if (group_sums) {
@@ -1393,6 +1402,7 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team,
             prev = __hip_atomic_fetch_add(&R.result->arrived, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         prev = uniform((uint32_t)__shfl((int)prev, 0, 64));
         if (prev != ngroups - 1) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (lane == 0) __hip_atomic_store(&R.result->arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     int32_t err = 0;
@@ -1409,41 +1419,87 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team,
     if (rec) publish_record(R, rec, lane);
 }
 
-/* Served form: wait until item `it` is published.  The host's published
- * count lives in host memory, so polling it crosses PCIe; only the
- * workgroup holding the next unpublished item (it == the device copy of
- * the count) polls the host, and it mirrors what it sees into device
- * memory, where every other waiting workgroup polls.  Polls are relaxed
- * (an acquire per poll would invalidate the L2 each time) and back off
- * with sleeps; once the item is seen, one agent-scope acquire makes the
- * request's device-memory inputs visible.  Returns false when the host
- * asked to stop or nothing arrived for idle_limit ticks, so every wave
- * reaches an exit. */
-__device__ __forceinline__ bool wait_published(const dsr_dlaunch &LP, uint32_t it, uint32_t lane)
+/* Served form: close the server (one workgroup does it; see wait_item).
+ * The device announces the close in host memory, then reads the host's
+ * published count once more: the host publishes, then reads the closing
+ * flag, so at least one side sees the other's write (both orders are
+ * sequentially consistent at system scope, and a read from the device to
+ * host memory does not pass the device's earlier write to it).  Every item
+ * below the count read here is served; none above it is.  The count is
+ * returned to the host, which takes back a request it published too late. */
+__device__ __forceinline__ void close_server(const dsr_dlaunch &LP)
+{
+    uint32_t *ctr = LP.counter;
+    uint32_t open = 0;
+    if (!__hip_atomic_compare_exchange_strong(ctr + DSR_SRV_STATE, &open, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT))
+        return;
+    __hip_atomic_store(LP.closing, 1u, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_SYSTEM);
+    __atomic_thread_fence(__ATOMIC_SEQ_CST);
+    const uint32_t h = __hip_atomic_load(LP.published, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_fetch_max(ctr + DSR_SRV_PUB, h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(ctr + DSR_SRV_FINAL, h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(LP.final_items, h + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(ctr + DSR_SRV_STATE, 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+/* Served form: wait until item `it` is published (true: run it) or the
+ * server has closed below it (false: leave).
+ *
+ * The host's published count lives in host memory, so polling it crosses
+ * PCIe; only the workgroup holding the next unpublished item (it == the
+ * device copy of the count) polls the host, and it mirrors what it sees
+ * into device memory, where every other waiting workgroup polls.  Polls
+ * are relaxed (an acquire per poll would invalidate the L2 each time) and
+ * back off with sleeps; once the item is seen, one agent-scope acquire
+ * makes the request's device-memory inputs visible.
+ *
+ * Closing is one decision for the whole server, never a workgroup's own:
+ * it happens when the host asks to stop, or when the device copy of the
+ * published count has not changed for idle_limit ticks (a clock shared by
+ * every workgroup).  The server then serves every item published before
+ * the close and no other, so a workgroup leaves only while holding an
+ * item nobody will publish to it, and no claimed item is lost.  Nothing
+ * here waits for another workgroup, so the server does not rely on its
+ * whole grid being resident at once. */
+__device__ __forceinline__ bool wait_item(const dsr_dlaunch &LP, uint32_t it, uint32_t lane)
 {
     uint32_t ok = 0;
     if (lane == 0) {
-        uint32_t *dpub = LP.counter + 16, *dstop = LP.counter + 32;
-        const uint64_t t0 = wall_clock64();
+        uint32_t *ctr = LP.counter;
+        uint64_t *last = (uint64_t *)(ctr + DSR_SRV_LAST);
         uint32_t nap = 0;
         for (;;) {
-            const uint32_t pub = __hip_atomic_load(dpub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t pub = __hip_atomic_load(ctr + DSR_SRV_PUB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (it < pub) { ok = 1; break; }
-            if (__hip_atomic_load(dstop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-            if (it == pub) {
-                const uint32_t h = __hip_atomic_load(LP.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                if (h != pub) {
-                    __hip_atomic_fetch_max(dpub, h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 1;
-                    break;
-                }
-                if (__hip_atomic_load(LP.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
-                    __hip_atomic_store(dstop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-                nap = 0;
+            const uint32_t st = __hip_atomic_load(ctr + DSR_SRV_STATE, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            if (st == 2) {
+                /* closed: items below the final count were made visible
+                 * through the published copy above; this one is beyond it */
+                if (it >= __hip_atomic_load(ctr + DSR_SRV_FINAL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                continue;
             }
-            if (wall_clock64() - t0 > LP.idle_limit) break;
+            if (st == 0) {
+                if (it == pub) {
+                    const uint32_t h = __hip_atomic_load(LP.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    if (h != pub) {
+                        __hip_atomic_fetch_max(ctr + DSR_SRV_PUB, h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(last, wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = 1;
+                        break;
+                    }
+                    if (__hip_atomic_load(LP.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+                        close_server(LP);
+                        continue;
+                    }
+                    nap = 0;
+                }
+                const uint64_t t_last = __hip_atomic_load(last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (wall_clock64() - t_last > LP.idle_limit) {
+                    close_server(LP);
+                    continue;
+                }
+            }
             /* s_sleep takes an immediate (64 * n clocks); workgroups whose
              * item is far from the next one published sleep longest */
             if (it - pub >= 64) {
@@ -1521,8 +1577,16 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
                          C.hbm_base + (uint64_t)blockIdx.x * C.hbm_slot_bytes, (uint32_t)C.hbm_slot_bytes);
     const bool single = LP.items == nullptr;
     uint32_t barriers = 0, inner_pushes = 0;
-    if (LP.published && blockIdx.x == 0 && T.wave == C.nw - 1 && T.lane == 0 && LP.done_ts)
-        __hip_atomic_store(LP.done_ts, wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (LP.published && T.wave == C.nw - 1 && T.lane == 0) {
+        const uint64_t now = wall_clock64();
+        if (blockIdx.x == 0 && LP.done_ts)
+            __hip_atomic_store(LP.done_ts, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        /* the idle clock starts with the first workgroup to run */
+        uint64_t zero = 0;
+        __hip_atomic_compare_exchange_strong((uint64_t *)(LP.counter + DSR_SRV_LAST), &zero, now,
+                                             __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(LP.wg_started + blockIdx.x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
     if (LP.start_ts && blockIdx.x == 0 && T.wave == C.nw - 1 && T.lane == 0) *LP.start_ts = wall_clock64();
     if (T.wave == C.nw - 1) {
         for (uint32_t round = 0;; ++round) {
@@ -1533,12 +1597,12 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
                 team = blockIdx.x;
             } else {
                 uint32_t it = 0;
-                if (T.lane == 0) it = atomicAdd(&LP.counter[0], 1u);
+                if (T.lane == 0) it = atomicAdd(&LP.counter[DSR_SRV_CLAIM], 1u);
                 it = uniform((uint32_t)__shfl((int)it, 0, 64));
                 if (LP.published) {
                     /* served form: wait until the host has published item
-                     * `it`; leave on stop or after idle_limit ticks without it */
-                    if (!wait_published(LP, it, T.lane)) break;
+                     * `it`; leave once the server has closed below it */
+                    if (!wait_item(LP, it, T.lane)) break;
                     const uint32_t k = it & LP.ring_mask;
                     region = uniform(__hip_atomic_load(&LP.items[2 * k], __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_SYSTEM));
@@ -1563,8 +1627,8 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
                                              LP.recs ? LP.recs + region : nullptr);
             if (tr && T.lane == 0) tr[88] = (uint32_t)wall_clock64();
         }
-        if (LP.exited && T.lane == 0)
-            __hip_atomic_fetch_add(LP.exited, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (LP.wg_exited && T.lane == 0)
+            __hip_atomic_store(LP.wg_exited + blockIdx.x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         /* terminate the workers (Figure 3's terminate branch) */
         frame_t none{SPACE_NONE, 0, 0};
         publish(T, none, DSR_BODY_TERMINATE, 0);

@@ -55,7 +55,7 @@ EXPORTS = ("dsr_init", "dsr_destroy", "dsr_region_begin", "dsr_push", "dsr_publi
            "dsr_batch_elapsed", "dsr_batch_free", "dsr_autotune", "dsr_batch_replay_serial",
            "dsr_serve_start", "dsr_serve_submit", "dsr_serve_poll", "dsr_serve_pending",
            "dsr_serve_replay", "dsr_serve_stop", "dsr_occupancy_model", "dsr_region_occupancy",
-           "dsr_publish_list", "dsr_control_bytes")
+           "dsr_publish_list", "dsr_control_bytes", "dsr_serve_status")
 
 
 class dsr_ref(C.Structure):
@@ -103,6 +103,15 @@ class dsr_done(C.Structure):
             fx.append(_fixed([w[0], w[1], w[2]]))
         return {"ticket": self.ticket, "status": self.status, "f64": list(self.f64[:self.n_red]),
                 "i64": list(self.i64[:self.n_red]), "fixed": fx, "device_us": self.device_us}
+
+
+class dsr_serve_stat(C.Structure):
+    _fields_ = [("grid", C.c_uint32), ("started", C.c_uint32), ("exited", C.c_uint32),
+                ("closed", C.c_uint32), ("final_items", C.c_uint32), ("published", C.c_uint32),
+                ("in_flight", C.c_uint32), ("pad", C.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
 class dsr_hw_model(C.Structure):
@@ -189,6 +198,7 @@ def lib():
                                  C.POINTER(P), i32, C.c_double, C.POINTER(C.c_double),
                                  C.POINTER(dsr_done)],
             "dsr_serve_stop": [P],
+            "dsr_serve_status": [P, C.POINTER(dsr_serve_stat)],
             "dsr_occupancy_model": [C.POINTER(dsr_hw_model), u32, u32, u32,
                                     C.POINTER(dsr_occupancy_t)],
             "dsr_region_occupancy": [P, u32, C.POINTER(dsr_occupancy_t)],
@@ -470,6 +480,12 @@ def dsr_serve_replay(server, programs, prog, arrival_s, slot_outs=None, n_loops_
 
 def dsr_serve_stop(server):
     return _check(lib().dsr_serve_stop(server), "dsr_serve_stop")
+
+
+def dsr_serve_status(server):
+    st = dsr_serve_stat()
+    _check(lib().dsr_serve_status(server, C.byref(st)), "dsr_serve_status")
+    return st.as_dict()
 
 
 # ---- footprint and occupancy model --------------------------------------------

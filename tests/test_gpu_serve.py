@@ -54,13 +54,41 @@ def submit_retry(srv, region, outs=None, sink=None, timeout=60.0):
             assert time.time() - t0 < timeout, "admission never freed up"
 
 
-def drain(srv, want, timeout=60.0):
+# A request of these sizes runs in tens of microseconds on the device; a
+# completion that takes longer than this means the server stalled.
+REQUEST_BOUND_S = 0.1
+
+
+def drain(srv, want, timeout=5.0):
     got = []
     t0 = time.time()
     while len(got) < want:
         got += D.dsr_serve_poll(srv)
         assert time.time() - t0 < timeout, "server did not finish"
     return got
+
+
+def wait_started(srv, timeout=2.0):
+    """Every workgroup of the server's grid runs: the device holds the
+    whole grid at once, as the occupancy query promised."""
+    t0 = time.time()
+    while True:
+        st = D.dsr_serve_status(srv)
+        if st["started"] == st["grid"]:
+            return st
+        assert time.time() - t0 < timeout, ("grid not resident", st)
+        time.sleep(0.001)
+
+
+def run_one(srv, region, outs=None):
+    """Submit one request and wait for it; returns (done, seconds)."""
+    t0 = time.perf_counter()
+    D.dsr_serve_submit(srv, region, outs)
+    got = []
+    while not got:
+        got = D.dsr_serve_poll(srv)
+        assert time.perf_counter() - t0 < 5.0, "request did not complete"
+    return got[0], time.perf_counter() - t0
 
 
 @pytest.fixture(scope="module")
@@ -85,16 +113,71 @@ def test_serve_output_visible_at_completion(setup):
     srv = D.dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=32768, slots=16, slot_bytes=40960,
                             max_teams=64, idle_ms=20000)
     try:
+        wait_started(srv)
         for k in range(12):
             ins, x, yr, rs, fx = insts[k]
             out = torch.zeros_like(ys[k])
             torch.cuda.current_stream().synchronize()
-            D.dsr_serve_submit(srv, regs[k], [out.data_ptr()])
-            d = drain(srv, 1)[0]
+            d, secs = run_one(srv, regs[k], [out.data_ptr()])
             assert d["status"] == 0 and d["f64"] == [rs]
+            assert secs < REQUEST_BOUND_S, (k, secs)
             assert np.array_equal(out.cpu().numpy().view(np.uint64), yr.view(np.uint64)), k
     finally:
         D.dsr_serve_stop(srv)
+
+
+def test_serve_light_load_and_idle_close(setup):
+    """One request every 50 ms for 1 s with a 200 ms idle limit: the
+    server keeps serving (idle means no new request for the whole server,
+    not one workgroup's wait), every request completes within the bound,
+    and 200 ms after the last one the server closes as a whole: every
+    workgroup leaves and a later submit is refused."""
+    ctx, insts, xs, ys, regs = setup
+    say("serve light load")
+    srv = D.dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=32768, slots=16, slot_bytes=40960,
+                            max_teams=64, idle_ms=200)
+    try:
+        wait_started(srv)
+        t_next = time.perf_counter()
+        for q in range(20):
+            while time.perf_counter() < t_next:
+                pass
+            t_next += 0.05
+            k = q % len(regs)
+            d, secs = run_one(srv, regs[k])
+            assert d["status"] == 0 and d["f64"] == [insts[k][3]], q
+            assert secs < REQUEST_BOUND_S, (q, secs)
+            st = D.dsr_serve_status(srv)
+            assert st["closed"] == 0 and st["exited"] == 0, (q, st)
+        time.sleep(0.6)
+        st = D.dsr_serve_status(srv)
+        assert st["closed"] == 1 and st["exited"] == st["grid"], st
+        assert st["final_items"] == st["published"], st
+        with pytest.raises(D.DsrError) as e:
+            D.dsr_serve_submit(srv, regs[0])
+        assert e.value.code == D.DSR_E_STATE
+    finally:
+        D.dsr_serve_stop(srv)
+
+
+def test_serve_stop_runs_published_requests(setup):
+    """Requests published before a stop all run to completion (the close
+    drains them), and the stop returns promptly."""
+    ctx, insts, xs, ys, regs = setup
+    say("serve stop drains")
+    outs = [torch.zeros_like(y) for y in ys[:16]]
+    torch.cuda.current_stream().synchronize()
+    srv = D.dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=32768, slots=16, slot_bytes=40960,
+                            max_teams=64, idle_ms=20000)
+    try:
+        for k in range(16):
+            D.dsr_serve_submit(srv, regs[k], [outs[k].data_ptr()])
+    finally:
+        t0 = time.perf_counter()
+        D.dsr_serve_stop(srv)
+        assert time.perf_counter() - t0 < 2.0
+    for k in range(16):
+        assert np.array_equal(outs[k].cpu().numpy().view(np.uint64), insts[k][2].view(np.uint64)), k
 
 
 def test_serve_requests_match_oracle(setup):
