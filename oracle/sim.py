@@ -14,38 +14,59 @@ A plain, slow model of one OpenMP target region in generic mode:
 * Sharing is by reference (section 5.1): workers read shared locals through
   (space, offset) into the simulated bytes every time they use them.
 * Reductions go into a shared variable held in the frame: each worker keeps
-  a private partial, stores it in its own control slot, and after the join
-  the master adds the partials, in worker order, into the frame's slot.
+  a private partial, and after the join the master adds the partials, in
+  worker order, into the frame's slot.  The fp64 reduction is an exact
+  rational sum, rounded once to nearest-even when the region's result is
+  read: the plain definition of "sum += y[i]" with no rounding in between.
 * Frames are popped in LIFO order and none may outlive the region.
+* Nested parallelism (section 3.1.2; section 7's sharing at worker level):
+  in a nested body each worker is the master of an inner team.  It pushes
+  an inner frame on its own member stack, hands it to its inner members and
+  pops it after they join; with three levels each inner member does the
+  same again on its own lane-group stack.  A member stack lives on chip
+  and overflows to the member's area of a global-memory stack when the
+  on-chip part is exhausted (section 7), else the region fails with NOMEM.
+
+Memory visibility.  Every thread has a private buffer of writes that the
+others cannot see yet; a synchronisation of a scope (the team barrier, or
+the barrier of one member's inner team) releases the buffered writes of
+every thread in that scope.  A thread reads shared memory overlaid with its
+own buffered writes.  So a worker that looked at a frame before the fork
+barrier would see stale bytes, and invariant I1 below compares what each
+worker actually sees with what its master wrote.
 
 Every step checks the invariants
-  I1 each worker's view of a published frame equals the master's bytes at
-     publish time,
+  I1 each worker's view of a published frame, taken at its await, equals
+     the master's view of it at publish time (at every nesting level),
   I2 frames pop in LIFO order,
   I3 no frame outlives its region (nor an inner frame its outer body),
   I4 stack bytes in use equal the sum of the live frames' rounded sizes,
   I5 stack pointers stay within capacity; out-of-memory happens exactly
      when a frame fits neither space,
-and a race detector that records, per byte, the last writer and the phase
-(barrier epoch) of the write, and flags a cross-thread access to a byte
-written in the same phase, any access outside a live frame and any access
-after a pop.
+and a race detector that records, per byte, the last writer and the epochs
+of the writer's scopes at the write, and flags a cross-thread access to a
+byte unless a synchronisation of a scope holding both threads came after
+the write, any access outside a live frame and any access after a pop.
 
 Loop bodies (their frame layouts are the bodies' contracts):
   affine_xor   [0,8) int64 sum slot; a, b, c, d int32 at 8, 12, 16, 20.
                out[i] = a*i + b - (c ^ i) + d (int32 wrap); sum += out[i].
-  fma_chain    [0,24) exact sum slot: signed 192-bit integer, units of
-               2**-75, little-endian 64-bit words; nf fp64 scalars at 24;
-               ni int32 scalars after them; optional int32 array of alen
-               elements at the next 16-byte boundary.
-               y[i] = fma chain (int32 scalars first, then fp64) over x[i]
-               starting from arr[i mod alen] (or +0.0); sum += y[i] exactly.
+  fma_chain    [0,24) exact sum slot; nf fp64 scalars at 24; ni int32
+               scalars after them; optional int32 array of alen elements at
+               the next 16-byte boundary.  y[i] = fma chain (int32 scalars
+               first, then fp64) over x[i] starting from arr[i mod alen]
+               (or +0.0); sum += y[i] exactly.
   gather       A int32 arrays of ``length`` elements back to back at 0.
                out[i] = sum_j arr_j[i mod length] + i.
-  gather_nested  as gather, but each outer member pushes a 16-byte inner
-               frame {lo, hi, stride, outer frame id} on its own sub-stack
-               and hands it to its inner members (a second, nested parallel
-               level), then pops it.
+  gather_nested  as gather, run as ``depth`` (2 or 3) nested parallel
+               levels.  Level 1: the workers split the team's range.  Each
+               pushes a 16-byte inner frame {lo, hi, parent space, parent
+               offset} on its member stack and hands it to its ``inner``
+               members; these split [lo, hi) again.  At depth 3 each of them
+               pushes a frame of the same shape, pointing at the inner
+               frame, on its own lane-group stack for its ``inner`` members.
+               The innermost members reach the team's frame by following
+               the parent references, then gather.
   fma_chain_refs the fma_chain loop published through a list of references
                (section 5.2): reference 0 is the 24-byte exact sum slot,
                then ni int32 scalars, nf fp64 scalars and, if alen > 0, the
@@ -55,9 +76,10 @@ Loop bodies (their frame layouts are the bodies' contracts):
                pushed at the fork and popped at the join.  Workers read a
                reference, then the variable through it, on every use.
 
-Sizes are rounded up to ``align`` (16) bytes; frame offsets are multiples
-of it.  Fractions give correctly rounded fma (one rounding of the exact
-a*b+c) independently of the C oracle.
+Sizes are rounded up to ``align`` bytes (8 by default: section 5.3.1 aligns
+the shared stack's variables to 8 bytes); frame offsets are multiples of
+it.  Fractions give correctly rounded fma (one rounding of the exact a*b+c)
+independently of the C oracle.
 """
 from dataclasses import dataclass, field
 from fractions import Fraction
@@ -67,18 +89,18 @@ import struct
 
 import numpy as np
 
-LDS, HBM, CTL = "lds", "hbm", "ctl"
+LDS, HBM, CTL, NLDS, NHBM = "lds", "hbm", "ctl", "nlds", "nhbm"
 REF_LIST_ENTRIES = 20             # references the on-chip list holds
 REF_BYTES = 8                     # a reference: space (u32), offset (u32)
 SLOT_F64_EXACT = 24
-UNIT_EXP = 75                     # exact sums are integers in units of 2**-75
-WINDOW_EXP = 32                   # |y| must be below 2**32
-INT192 = 1 << 192
+NEST_FRAME = 16                   # {lo, hi, parent space, parent offset}
+UNIT_EXP = 75                     # the slot's bytes: a 192-bit integer of 2**-75 units
+TEAM = "team"
 
 
 class SimError(Exception):
     """A runtime error; ``code`` is one of NOMEM, ORDER, UNDERFLOW, LIVE,
-    STATE, INVAL, RANGE."""
+    STATE, INVAL."""
 
     def __init__(self, code, msg=""):
         super().__init__("%s: %s" % (code, msg))
@@ -95,10 +117,13 @@ class Config:
     lds_bytes: int = 65536        # on-chip stack capacity per team
     hbm_bytes: int = 1 << 20      # global-memory stack capacity per team
     threshold: int = 1 << 30      # largest frame placed on chip
-    workers: int = 3              # worker threads per team
-    sub_bytes: int = 64           # per outer member sub-stack (nested level)
-    inner: int = 4                # inner members per outer member
-    align: int = 16
+    workers: int = 3              # worker threads per team (level-1 members)
+    inner: int = 4                # inner members per member, at each nested level
+    wave_lds: int = 64            # on-chip part of a level-1 member's stack
+    wave_hbm: int = 256           # its global-memory part
+    group_lds: int = 16           # on-chip part of a level-2 member's stack
+    group_hbm: int = 64           # its global-memory part
+    align: int = 8
     schedule: str = "cyclic"      # iteration -> worker: block cyclic reverse random
     interleave: str = "canonical" # step order: canonical roundrobin random
     seed: int = 0
@@ -132,18 +157,18 @@ class Pop:
 
 @dataclass
 class FrameRec:
-    fid: int
+    fid: object
     space: str
     off: int
     size: int                     # rounded size
     nbytes: int                   # declared size
-    owner: str                    # "team" or "outer<m>"
+    owner: str                    # "team" or the member that pushed it
 
 
 @dataclass
 class TeamTrace:
     placements: list = field(default_factory=list)   # (space, off, size) per push
-    sub_placements: list = field(default_factory=list)
+    sub_placements: list = field(default_factory=list)  # (level, member, space, off, size)
     lists: list = field(default_factory=list)        # (space, off, entries) per list publish
     master_barriers: int = 0
     worker_barriers: list = field(default_factory=list)
@@ -160,20 +185,6 @@ def fma(a, b, c):
     return float(Fraction(a) * Fraction(b) + Fraction(c))
 
 
-def to_units(y):
-    """y as an integer number of 2**-75 units, or None when y is off the
-    2**-75 grid or |y| >= 2**32."""
-    if y != y or y in (float("inf"), float("-inf")) or abs(y) >= 2.0 ** WINDOW_EXP:
-        return None
-    f = Fraction(y) * (1 << UNIT_EXP)
-    return f.numerator if f.denominator == 1 else None
-
-
-def units_to_float(u):
-    """Correctly rounded double of u * 2**-75 (u a Python int)."""
-    return float(Fraction(u, 1 << UNIT_EXP))
-
-
 def int_to_le(v, nbytes):
     return (v % (1 << (8 * nbytes))).to_bytes(nbytes, "little")
 
@@ -183,14 +194,74 @@ def le_to_int(b):
     return v - (1 << (8 * len(b))) if v >> (8 * len(b) - 1) else v
 
 
+def scopes_of(who):
+    """The synchronisation scopes holding thread ``who``, outermost first:
+    the team, then each member whose inner team it belongs to, then its own
+    inner team (a member is the master of the team it forks)."""
+    if who == "master":
+        return [TEAM]
+    parts = who.split(".")
+    return [TEAM] + [".".join(parts[:k]) for k in range(1, len(parts) + 1)]
+
+
 class Memory:
-    """Byte store of one space with per-byte shadow (writer, phase, alive)."""
+    """Byte store of one space with a per-byte shadow: the last writer and
+    the epochs of its scopes at the write."""
 
     def __init__(self, name, size):
         self.name = name
         self.data = bytearray(size)
-        self.writer = [None] * size
-        self.phase = [-1] * size
+        self.shadow = [None] * size
+
+
+class MemberStack:
+    """A nested member's stack: an on-chip part and a global-memory part,
+    each a LIFO bump region at a fixed base of the team's nested areas."""
+
+    def __init__(self, team, owner, level, lds_base, lds_cap, hbm_base, hbm_cap):
+        self.team, self.owner, self.level = team, owner, level
+        self.base = {NLDS: lds_base, NHBM: hbm_base}
+        self.cap = {NLDS: lds_cap, NHBM: hbm_cap}
+        self.sp = {NLDS: 0, NHBM: 0}
+        self.frames = []
+
+    def check(self):
+        used = {NLDS: 0, NHBM: 0}
+        for f in self.frames:
+            used[f.space] += f.size
+        for s in (NLDS, NHBM):
+            if used[s] != self.sp[s]:
+                raise Violation("I4: %s stack of %s: %d bytes, live frames %d"
+                                % (s, self.owner, self.sp[s], used[s]))
+            if self.sp[s] > self.cap[s]:
+                raise Violation("I5: %s stack of %s beyond capacity" % (s, self.owner))
+
+    def push(self, nbytes):
+        size = round_up(nbytes, self.team.cfg.align)
+        if self.sp[NLDS] + size <= self.cap[NLDS]:
+            space = NLDS
+        elif self.sp[NHBM] + size <= self.cap[NHBM]:
+            space = NHBM
+        else:
+            raise SimError("NOMEM", "nested frame of %d bytes fits neither stack of %s" % (size, self.owner))
+        f = FrameRec(("nest", self.owner, len(self.team.trace.sub_placements)), space,
+                     self.base[space] + self.sp[space], size, nbytes, self.owner)
+        self.sp[space] += size
+        self.frames.append(f)
+        self.team.fresh(f)
+        self.team.trace.sub_placements.append((self.level, self.owner, space, f.off, size))
+        self.check()
+        return f
+
+    def pop(self, f):
+        if not self.frames:
+            raise SimError("UNDERFLOW", "pop on the empty stack of %s" % self.owner)
+        if self.frames[-1] is not f:
+            raise SimError("ORDER", "nested pop of a frame that is not the top")
+        self.frames.pop()
+        self.sp[f.space] -= f.size
+        self.team.dead.add(f.fid)
+        self.check()
 
 
 class Team:
@@ -198,15 +269,20 @@ class Team:
         self.tid = tid
         self.cfg = cfg
         self.n_teams = n_teams
+        m, g = cfg.workers, cfg.inner
         self.mem = {LDS: Memory(LDS, cfg.lds_bytes), HBM: Memory(HBM, cfg.hbm_bytes),
-                    CTL: Memory(CTL, REF_LIST_ENTRIES * REF_BYTES)}
+                    CTL: Memory(CTL, REF_LIST_ENTRIES * REF_BYTES),
+                    NLDS: Memory(NLDS, m * cfg.wave_lds + m * g * cfg.group_lds),
+                    NHBM: Memory(NHBM, m * cfg.wave_hbm + m * g * cfg.group_hbm)}
         self.sp = {LDS: 0, HBM: 0}
         self.frames = []           # live team-level frames, bottom .. top
         self.by_id = {}
         self.dead = set()
-        self.phase = 0
+        self.epoch = {TEAM: 0}
+        self.pending = {}          # thread -> {(space, byte): value} not yet released
+        self.exact = {}            # (space, offset) -> exact value of an fp64 sum slot
+        self.members = {}          # owner -> MemberStack
         self.trace = TeamTrace(worker_barriers=[0] * cfg.workers)
-        self.live_ranges = {LDS: [], HBM: []}   # (off, end) of live frames
 
     # -- invariants -------------------------------------------------------
     def check_stack(self):
@@ -219,56 +295,106 @@ class Team:
         if self.sp[LDS] > self.cfg.lds_bytes or self.sp[HBM] > self.cfg.hbm_bytes:
             raise Violation("I5: stack pointer beyond capacity")
 
-    # -- memory access through (space, offset) -----------------------------
-    def _frame_covering(self, space, off, n):
-        for f in self.frames:
-            if f.space == space and f.off <= off and off + n <= f.off + f.size:
-                return f
-        return None
+    def live_frames(self):
+        out = list(self.frames)
+        for ms in self.members.values():
+            out += ms.frames
+        return out
 
+    # -- synchronisation --------------------------------------------------
+    def sync(self, scope):
+        """Release the buffered writes of every thread in ``scope`` and
+        start a new epoch of it (a barrier of that scope)."""
+        for who in list(self.pending):
+            if scope == TEAM or who == scope or who.startswith(scope + "."):
+                for (space, b), v in self.pending.pop(who).items():
+                    self.mem[space].data[b] = v
+        self.epoch[scope] = self.epoch.get(scope, 0) + 1
+
+    def barrier(self, participants="all"):
+        self.sync(TEAM)
+        self.trace.master_barriers += 1
+        for w in range(self.cfg.workers):
+            self.trace.worker_barriers[w] += 1
+
+    def ordered(self, rec, who):
+        """Whether a write recorded as ``rec`` happens before an access by
+        ``who``: same thread, or a later sync of a scope holding both."""
+        writer, snap = rec
+        if writer == who:
+            return True
+        for s in scopes_of(who):
+            if s in snap and self.epoch.get(s, 0) > snap[s]:
+                return True
+        return False
+
+    # -- memory access through (space, offset) -----------------------------
     def access(self, space, off, n, who, write, data=None, frames=None):
-        pool = self.frames if frames is None else frames
+        pool = self.live_frames() if frames is None else frames
         ok = any(f.space == space and f.off <= off and off + n <= f.off + f.size for f in pool)
         if not ok:
             raise Violation("race detector: %s access [%d,%d) of %s outside a live frame"
                             % (who, off, off + n, space))
         m = self.mem[space]
         for b in range(off, off + n):
-            w, p = m.writer[b], m.phase[b]
-            if w is not None and w != who and p == self.phase:
-                raise Violation("race detector: %s %s byte %d of %s written by %s in phase %d"
-                                % (who, "writes" if write else "reads", b, space, w, p))
+            rec = m.shadow[b]
+            if rec is not None and not self.ordered(rec, who):
+                raise Violation("race detector: %s %s byte %d of %s written by %s with no sync between"
+                                % (who, "writes" if write else "reads", b, space, rec[0]))
         if write:
-            m.data[off:off + n] = data
-            for b in range(off, off + n):
-                m.writer[b] = who
-                m.phase[b] = self.phase
+            buf = self.pending.setdefault(who, {})
+            snap = {s: self.epoch.get(s, 0) for s in scopes_of(who)}
+            for k in range(n):
+                buf[(space, off + k)] = data[k]
+                m.shadow[off + k] = (who, snap)
             return None
-        return bytes(m.data[off:off + n])
+        return self.view(space, off, n, who)
+
+    def view(self, space, off, n, who):
+        """Bytes [off, off+n) of ``space`` as thread ``who`` sees them."""
+        buf = self.pending.get(who, {})
+        d = self.mem[space].data
+        return bytes(buf.get((space, b), d[b]) for b in range(off, off + n))
+
+    def frame_view(self, f, who):
+        return hashlib.sha256(self.view(f.space, f.off, f.nbytes, who)).hexdigest()
+
+    def fresh(self, f):
+        """A newly pushed frame holds no one's data."""
+        m = self.mem[f.space]
+        for b in range(f.off, f.off + f.size):
+            m.shadow[b] = None
+        for k in [k for k in self.exact if k[0] == f.space and f.off <= k[1] < f.off + f.size]:
+            del self.exact[k]
 
     def read(self, f, off, n, who, frames=None):
         if f.fid in self.dead:
-            raise Violation("race detector: %s reads frame %d after its pop" % (who, f.fid))
+            raise Violation("race detector: %s reads frame %r after its pop" % (who, f.fid))
         if off < 0 or off + n > f.nbytes:
-            raise Violation("race detector: %s reads [%d,%d) outside frame %d of %d bytes"
+            raise Violation("race detector: %s reads [%d,%d) outside frame %r of %d bytes"
                             % (who, off, off + n, f.fid, f.nbytes))
         return self.access(f.space, f.off + off, n, who, False, frames=frames)
 
     def write(self, f, off, data, who, frames=None):
         if f.fid in self.dead:
-            raise Violation("race detector: %s writes frame %d after its pop" % (who, f.fid))
+            raise Violation("race detector: %s writes frame %r after its pop" % (who, f.fid))
         if off < 0 or off + len(data) > f.nbytes:
-            raise Violation("race detector: %s writes outside frame %d" % (who, f.fid))
+            raise Violation("race detector: %s writes outside frame %r" % (who, f.fid))
         self.access(f.space, f.off + off, len(data), who, True, data, frames=frames)
 
-    def barrier(self, participants):
-        self.phase += 1
-        self.trace.master_barriers += 1
-        for w in range(self.cfg.workers):
-            self.trace.worker_barriers[w] += 1
+    # -- exact fp64 sum slots ----------------------------------------------
+    def read_exact(self, space, off, who):
+        raw = self.access(space, off, SLOT_F64_EXACT, who, False)
+        if (space, off) in self.exact:
+            return self.exact[(space, off)]
+        return Fraction(le_to_int(raw), 1 << UNIT_EXP)
 
-    def frame_hash(self, f):
-        return hashlib.sha256(bytes(self.mem[f.space].data[f.off:f.off + f.nbytes])).hexdigest()
+    def write_exact(self, space, off, value, who):
+        """The slot holds the exact value; its bytes hold the value's
+        2**-75-unit encoding (truncated when it is off that grid)."""
+        self.exact[(space, off)] = value
+        units = (value.numerator << UNIT_EXP) // value.denominator
+        self.access(space, off, SLOT_F64_EXACT, who, True, int_to_le(units, SLOT_F64_EXACT))
 
     # -- stack operations (master only) -----------------------------------
     def push(self, fid, nbytes, global_only=False):
@@ -288,10 +414,7 @@ class Team:
         self.by_id[fid] = f
         if not global_only:
             self.trace.placements.append((space, f.off, size))
-        m = self.mem[space]
-        for b in range(f.off, f.off + size):   # a new frame holds no one's data
-            m.writer[b] = None
-            m.phase[b] = -1
+        self.fresh(f)
         self.check_stack()
         return f
 
@@ -307,6 +430,24 @@ class Team:
         self.sp[f.space] -= f.size
         self.dead.add(fid)
         self.check_stack()
+
+    # -- nested member stacks ------------------------------------------------
+    def wave_stack(self, m):
+        c = self.cfg
+        key = "w%d" % m
+        if key not in self.members:
+            self.members[key] = MemberStack(self, key, 2, m * c.wave_lds, c.wave_lds, m * c.wave_hbm, c.wave_hbm)
+        return self.members[key]
+
+    def group_stack(self, m, g):
+        c = self.cfg
+        key = "w%d.g%d" % (m, g)
+        if key not in self.members:
+            k = m * c.inner + g
+            self.members[key] = MemberStack(self, key, 3, c.workers * c.wave_lds + k * c.group_lds,
+                                            c.group_lds, c.workers * c.wave_hbm + k * c.group_hbm,
+                                            c.group_hbm)
+        return self.members[key]
 
 
 # ---- iteration schedules -------------------------------------------------
@@ -364,6 +505,12 @@ def all_interleavings(queues):
     yield from rec([0] * len(n))
 
 
+def split(lo, hi, parts, k):
+    """Part k of [lo, hi) cut into ``parts`` contiguous pieces."""
+    per = -(-(hi - lo) // parts) if hi > lo else 0
+    return min(hi, lo + k * per), min(hi, lo + (k + 1) * per)
+
+
 # ---- loop bodies ---------------------------------------------------------
 def team_range(loop, tid, n_teams):
     n = loop["n"]
@@ -383,7 +530,7 @@ def _f64(b):
 class Body:
     """One outlined parallel body: reads the frame through its references,
     writes its output element, returns its reduction contribution."""
-    has_reduction = False
+    reduction = None              # None, "i64" or "exact"
     slot_bytes = 0
 
     def iteration(self, team, f, who, i, loop):
@@ -391,7 +538,7 @@ class Body:
 
 
 class AffineXor(Body):
-    has_reduction = True
+    reduction = "i64"
     slot_bytes = 8
 
     def iteration(self, team, f, who, i, loop):
@@ -408,7 +555,7 @@ class AffineXor(Body):
 
 
 class FmaChain(Body):
-    has_reduction = True
+    reduction = "exact"
     slot_bytes = SLOT_F64_EXACT
 
     def iteration(self, team, f, who, i, loop):
@@ -423,26 +570,38 @@ class FmaChain(Body):
         for k in range(nf):
             acc = fma(_f64(team.read(f, SLOT_F64_EXACT + 8 * k, 8, who)), xi, acc)
         loop["y"][i] = acc
-        u = to_units(acc)
-        if u is None:
-            raise SimError("RANGE", "y[%d] = %r is outside the exact-sum window" % (i, acc))
-        return u
+        return exact(acc, i)
+
+
+def exact(y, i):
+    if y != y or y in (float("inf"), float("-inf")):
+        raise SimError("INVAL", "y[%d] = %r has no exact sum" % (i, y))
+    return Fraction(y)
+
+
+def gather_at(team, space, off, who, i, loop):
+    """out[i] from A arrays of ``length`` int32 at (space, off)."""
+    A, length = loop["A"], loop["length"]
+    s = i
+    for j in range(A):
+        s += _i32(team.access(space, off + 4 * (j * length + i % length), 4, who, False))
+    loop["out"][i] = ((s + (1 << 31)) % (1 << 32)) - (1 << 31)
+    return 0
 
 
 class Gather(Body):
-    def iteration(self, team, f, who, i, loop, frames=None):
-        A, length = loop["A"], loop["length"]
-        s = i
-        for j in range(A):
-            s += _i32(team.read(f, 4 * (j * length + i % length), 4, who, frames=frames))
-        loop["out"][i] = ((s + (1 << 31)) % (1 << 32)) - (1 << 31)
-        return 0
+    def iteration(self, team, f, who, i, loop):
+        if f.fid in team.dead:
+            raise Violation("race detector: %s reads frame %r after its pop" % (who, f.fid))
+        if 4 * loop["A"] * loop["length"] > f.nbytes:
+            raise Violation("race detector: arrays beyond frame %r" % (f.fid,))
+        return gather_at(team, f.space, f.off, who, i, loop)
 
 
 class FmaChainRefs(Body):
     """fma_chain through references: every variable is reached by reading
     its reference from the list, then the variable (section 5.2)."""
-    has_reduction = True
+    reduction = "exact"
     slot_bytes = SLOT_F64_EXACT
 
     def iteration(self, team, lst, who, i, loop):
@@ -459,16 +618,13 @@ class FmaChainRefs(Body):
             sp, off = lst.ref(team, 1 + ni + k, who)
             acc = fma(_f64(team.access(sp, off, 8, who, False)), xi, acc)
         loop["y"][i] = acc
-        u = to_units(acc)
-        if u is None:
-            raise SimError("RANGE", "y[%d] = %r is outside the exact-sum window" % (i, acc))
-        return u
+        return exact(acc, i)
 
 
 BODIES = {"affine_xor": AffineXor(), "fma_chain": FmaChain(), "gather": Gather(),
           "gather_nested": Gather(), "fma_chain_refs": FmaChainRefs()}
-SPACE_CODE = {LDS: 0, HBM: 1}
-CODE_SPACE = {0: LDS, 1: HBM}
+SPACE_CODE = {LDS: 0, HBM: 1, NLDS: 4, NHBM: 5}
+CODE_SPACE = {v: k for k, v in SPACE_CODE.items()}
 
 
 class RefList:
@@ -486,12 +642,14 @@ class RefList:
             raise Violation("reference %d names no space" % k)
         return CODE_SPACE[code], off
 
-    def view(self, team, n, sizes):
-        """Bytes of the list and of every variable it references."""
-        h = hashlib.sha256(bytes(team.mem[self.frame.space].data[self.frame.off:self.frame.off + REF_BYTES * n]))
+    def view(self, team, n, sizes, who):
+        """Bytes of the list and of every variable it references, as
+        thread ``who`` sees them."""
+        lst = team.view(self.frame.space, self.frame.off, REF_BYTES * n, who)
+        h = hashlib.sha256(lst)
         for k in range(n):
-            code, off = struct.unpack_from("<II", team.mem[self.frame.space].data, self.frame.off + REF_BYTES * k)
-            h.update(bytes(team.mem[CODE_SPACE[code]].data[off:off + sizes[k]]))
+            code, off = struct.unpack_from("<II", lst, REF_BYTES * k)
+            h.update(team.view(CODE_SPACE[code], off, sizes[k], who))
         return h.hexdigest()
 
 
@@ -540,35 +698,47 @@ def run_team(team, program, interleaving=None):
     return team.trace
 
 
+def check_views(team, who_list, expect, view):
+    for w in who_list:
+        if view(w) != expect:
+            raise Violation("I1: %s sees a frame different from its master's" % w)
+
+
+def combine(team, body, slot_space, slot_off, partial):
+    """After the join: the master adds the workers' partials, in worker
+    order, into the shared slot."""
+    if body.reduction == "i64":
+        cur = le_to_int(team.access(slot_space, slot_off, 8, "master", False))
+        total = ((cur + sum(partial) + (1 << 63)) % (1 << 64)) - (1 << 63)
+        team.access(slot_space, slot_off, 8, "master", True, int_to_le(total, 8))
+    else:
+        total = team.read_exact(slot_space, slot_off, "master") + sum(partial, Fraction(0))
+        team.write_exact(slot_space, slot_off, total, "master")
+    team.trace.partials.append(total)
+
+
 def publish(team, f, op, rng, interleaving):
     cfg = team.cfg
     body = BODIES[op.body]
     loop = op.loop
-    master_view = team.frame_hash(f)
+    master_view = team.frame_view(f, "master")
     team.barrier("all")                                   # fork: release workers
-    for w in range(cfg.workers):                          # I1 at await
-        if team.frame_hash(f) != master_view:
-            raise Violation("I1: worker %d sees a frame different from the master's" % w)
+    check_views(team, ["w%d" % w for w in range(cfg.workers)], master_view,
+                lambda w: team.frame_view(f, w))          # I1 at await
     lo, hi = team_range(loop, team.tid, team.n_teams)
     partial = [0] * cfg.workers
     if op.body == "gather_nested":
-        run_nested(team, f, loop, lo, hi, rng)
+        run_nested(team, f, loop, lo, hi)
     else:
         queues = assign(range(lo, hi), cfg.workers, cfg.schedule, rng)
         steps = interleaving(queues) if interleaving else interleave(queues, cfg.interleave, rng)
         for w, i in steps:
             partial[w] += body.iteration(team, f, "w%d" % w, i, loop)
-    # end of parallel: each worker stores its private partial in its own
-    # control slot; the join barrier lets the master combine them
+    # end of parallel: each worker keeps its private partial; the join
+    # barrier lets the master combine them
     team.barrier("all")
-    if body.has_reduction:
-        nb = body.slot_bytes
-        cur = le_to_int(team.read(f, 0, nb, "master"))
-        total = cur + sum(partial)
-        if nb == 8:
-            total = ((total + (1 << 63)) % (1 << 64)) - (1 << 63)
-        team.write(f, 0, int_to_le(total, nb), "master")
-        team.trace.partials.append(total)
+    if body.reduction:
+        combine(team, body, f.space, f.off, partial)
     else:
         team.trace.partials.append(None)
 
@@ -602,10 +772,7 @@ def publish_list(team, pushed, op, rng, interleaving):
     n = len(entries)
     if n <= REF_LIST_ENTRIES:
         lf = FrameRec("list", CTL, 0, REF_LIST_ENTRIES * REF_BYTES, REF_BYTES * n, "team")
-        m = team.mem[CTL]
-        for b in range(REF_BYTES * n):
-            m.writer[b] = None
-            m.phase[b] = -1
+        team.fresh(lf)
         team.access(CTL, 0, REF_BYTES * n, "master", True, b"".join(entries), frames=[lf])
         global_list = None
     else:
@@ -616,11 +783,10 @@ def publish_list(team, pushed, op, rng, interleaving):
     lst = RefList(lf)
     body = BODIES[op.body]
     loop = op.loop
-    master_view = lst.view(team, n, sizes)
+    master_view = lst.view(team, n, sizes, "master")
     team.barrier("all")                                   # fork: release workers
-    for w in range(cfg.workers):                          # I1 at await
-        if lst.view(team, n, sizes) != master_view:
-            raise Violation("I1: worker %d sees a list or variable different from the master's" % w)
+    check_views(team, ["w%d" % w for w in range(cfg.workers)], master_view,
+                lambda w: lst.view(team, n, sizes, w))    # I1 at await
     lo, hi = team_range(loop, team.tid, team.n_teams)
     partial = [0] * cfg.workers
     queues = assign(range(lo, hi), cfg.workers, cfg.schedule, rng)
@@ -629,45 +795,83 @@ def publish_list(team, pushed, op, rng, interleaving):
         partial[w] += body.iteration(team, lst, "w%d" % w, i, loop)
     team.barrier("all")                                   # join
     sp, off = lst.ref(team, 0, "master")
-    cur = le_to_int(team.access(sp, off, SLOT_F64_EXACT, "master", False))
-    total = cur + sum(partial)
-    team.access(sp, off, SLOT_F64_EXACT, "master", True, int_to_le(total, SLOT_F64_EXACT))
-    team.trace.partials.append(total)
+    combine(team, body, sp, off, partial)
     if global_list is not None:
         team.pop(global_list)
 
 
-def run_nested(team, outer_frame, loop, lo, hi, rng):
-    """Second parallel level: the workers of the outer body are outer
-    members; each pushes an inner frame on its own sub-stack, hands it to
-    its inner members, and pops it after they finish."""
+def nested_fork(team, stack, who, lo, hi, parent):
+    """Member ``who`` pushes the frame {lo, hi, parent ref} on its own
+    stack and releases it to its inner members (their barrier)."""
+    f = stack.push(NEST_FRAME)
+    team.write(f, 0, struct.pack("<IIII", lo, hi, SPACE_CODE[parent.space], parent.off), who)
+    view = team.frame_view(f, who)
+    team.sync(who)
+    return f, view
+
+
+def read_nested(team, f, who):
+    lo, hi, code, off = struct.unpack("<IIII", team.read(f, 0, NEST_FRAME, who))
+    if code not in CODE_SPACE:
+        raise Violation("nested frame names no space")
+    return lo, hi, CODE_SPACE[code], off
+
+
+def frame_at(team, space, off):
+    """The live frame that starts at (space, off): what a reference names."""
+    for f in team.live_frames():
+        if f.space == space and f.off == off:
+            return f
+    raise Violation("reference to (%s, %d) names no live frame" % (space, off))
+
+
+def run_nested(team, outer_frame, loop, lo, hi):
+    """Nested levels below the team's fork (see gather_nested above): every
+    member is the master of an inner team, shares a frame with it through
+    its own stack, and pops the frame after the inner team joins."""
     cfg = team.cfg
-    members = cfg.workers
-    span = -(-(hi - lo) // members) if hi > lo else 0
-    for m in range(members):
-        mlo, mhi = min(hi, lo + m * span), min(hi, lo + (m + 1) * span)
+    depth = loop.get("depth", 2)
+    if depth not in (2, 3):
+        raise SimError("INVAL", "nesting depth %r" % depth)
+    for m in range(cfg.workers):
         who = "w%d" % m
-        sub = Memory("sub%d" % m, cfg.sub_bytes)
-        size = round_up(16, cfg.align)
-        if size > cfg.sub_bytes:
-            raise SimError("NOMEM", "inner frame does not fit the sub-stack")
-        team.trace.sub_placements.append(("sub%d" % m, 0, size))
-        inner = struct.pack("<iiii", mlo, mhi, cfg.inner, outer_frame.fid)
-        sub.data[0:16] = inner
-        # inner members read the inner frame, then run their share
-        for g in range(cfg.inner):
-            vlo, vhi, stride, ref = struct.unpack("<iiii", bytes(sub.data[0:16]))
-            if ref != outer_frame.fid:
-                raise Violation("inner frame lost its outer reference")
-            for i in range(vlo + g, vhi, stride):
-                BODIES["gather"].iteration(team, outer_frame, who, i, loop)
+        mlo, mhi = split(lo, hi, cfg.workers, m)
+        ws = team.wave_stack(m)
+        f2, v2 = nested_fork(team, ws, who, mlo, mhi, outer_frame)
+        inner = ["%s.g%d" % (who, g) for g in range(cfg.inner)]
+        check_views(team, inner, v2, lambda w: team.frame_view(f2, w))     # I1, level 2
+        for g, gwho in enumerate(inner):
+            vlo, vhi, psp, poff = read_nested(team, f2, gwho)
+            glo, ghi = split(vlo, vhi, cfg.inner, g)
+            if depth == 2:
+                for i in range(glo, ghi):
+                    gather_at(team, psp, poff, gwho, i, loop)
+                continue
+            gs = team.group_stack(m, g)
+            f3, v3 = nested_fork(team, gs, gwho, glo, ghi, f2)
+            leaves = ["%s.s%d" % (gwho, s) for s in range(cfg.inner)]
+            check_views(team, leaves, v3, lambda w: team.frame_view(f3, w))  # I1, level 3
+            for s, swho in enumerate(leaves):
+                slo, shi, qsp, qoff = read_nested(team, f3, swho)
+                _, _, osp, ooff = read_nested(team, frame_at(team, qsp, qoff), swho)
+                a, b = split(slo, shi, cfg.inner, s)
+                for i in range(a, b):
+                    gather_at(team, osp, ooff, swho, i, loop)
+            team.sync(gwho)                                # inner join
+            gs.pop(f3)
+        team.sync(who)                                     # inner join
+        ws.pop(f2)
+    for ms in team.members.values():                       # I3 for nested frames
+        if ms.frames:
+            raise Violation("I3: a nested frame of %s outlives its body" % ms.owner)
 
 
 def run_region(program, n_teams, cfg=None, interleaving=None):
     """Run ``program`` (list of Push/Publish/Pop) on ``n_teams`` teams.
     Returns (traces, reductions): reductions[p] is the p-th reducing
-    publish's value combined over teams (int64 wrap for affine_xor, a
-    correctly rounded float for fma_chain), or None if any team failed."""
+    publish's value combined over teams (int64 wrap for affine_xor, the
+    exact sum rounded once to nearest-even double for the fma chains), or
+    None if any team failed."""
     cfg = cfg or Config()
     traces = []
     for t in range(n_teams):
@@ -677,15 +881,16 @@ def run_region(program, n_teams, cfg=None, interleaving=None):
     if any(tr.error for tr in traces):
         return traces, None
     for p, op in enumerate(pubs):
-        if not BODIES[op.body].has_reduction:
+        kind = BODIES[op.body].reduction
+        if not kind:
             reductions.append(None)
             continue
         vals = [tr.partials[p] for tr in traces]
-        if op.body == "affine_xor":
+        if kind == "i64":
             s = sum(vals)
             reductions.append(((s + (1 << 63)) % (1 << 64)) - (1 << 63))
         else:
-            reductions.append(units_to_float(sum(vals)))
+            reductions.append(float(sum(vals, Fraction(0))))
     return traces, reductions
 
 

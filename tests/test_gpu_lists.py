@@ -87,7 +87,7 @@ def test_list_publish(ni, nf, alen, lds, flags):
     assert D.dsr_region_sync(r) == 0
     check(r, x_np, s_i, s_f, y, arr)
     # placement of the list against the simulator's
-    cfg = S.Config(lds_bytes=lds, hbm_bytes=8192)
+    cfg = S.Config(lds_bytes=lds, hbm_bytes=8192, align=16)   # the kernel's frame rounding
     ys = np.zeros(64)
     prog = [S.Push(size, init),
             S.PublishList(refs, "fma_chain_refs", {"n": 64, "x": x_np[:64], "y": ys, "ni": ni, "nf": nf,

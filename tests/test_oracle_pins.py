@@ -199,7 +199,8 @@ def test_sim_cfg1_every_schedule(sched, order):
     assert red == [rs] == [closed_form_sum(c.a, c.b, c.c, c.d)]
     assert np.array_equal(out, ro)
     for t in tr:
-        assert t.error is None and t.placements == [("lds", 0, 32)]
+        # section 5.3.1 aligns the stack to 8 bytes: the 24-byte frame takes 24
+        assert t.error is None and t.placements == [("lds", 0, 24)]
         # Figures 2 and 3: two barriers per parallel region, one to end
         assert t.master_barriers == 3 and t.worker_barriers == [3, 3, 3]
 
@@ -250,7 +251,8 @@ def test_sim_gather_nested_and_spill():
         assert np.array_equal(out, R.gather(arrs, 0, n))
         want_space = "lds" if lds >= 128 else "hbm"
         assert all(t.placements == [(want_space, 0, 128)] for t in tr)
-        assert all(len(t.sub_placements) == 3 for t in tr)
+        # one 16-byte inner frame per worker, on chip at its own stack's base
+        assert all(t.sub_placements == [(2, "w%d" % m, "nlds", 64 * m, 16) for m in range(3)] for t in tr)
 
 
 def test_sim_runtime_errors():
@@ -271,14 +273,21 @@ def test_sim_runtime_errors():
         assert red is None and all(t.error == code for t in tr), (prog, code)
 
 
-def test_sim_range_error_off_grid():
-    x = np.array([2.0**-30] * 4, np.float32)
-    y = np.zeros(4)
-    size, _ = S.fma_chain_layout(0, 1, 0)
-    prog = [S.Push(size, S.fma_chain_init([], [2.0**-50])),
-            S.Publish(0, "fma_chain", {"n": 4, "x": x, "y": y, "ni": 0, "nf": 1}), S.Pop(0)]
-    tr, red = S.run_region(prog, 1)
-    assert tr[0].error == "RANGE"
+def test_sim_exact_sum_has_no_window():
+    # the reduction is the exact sum of the y, rounded once: values off the
+    # kernel's 2**-75 grid, or beyond 2**32, are summed exactly all the same
+    # (the kernel reports such values as a range error instead)
+    x = np.array([2.0**-30, 1.5, -1.5, 2.0**-30, 3.0], np.float32)
+    y = np.zeros(5)
+    size, _ = S.fma_chain_layout(0, 2, 0)
+    prog = [S.Push(size, S.fma_chain_init([], [2.0**-50, 2.0**40])),
+            S.Publish(0, "fma_chain", {"n": 5, "x": x, "y": y, "ni": 0, "nf": 2}), S.Pop(0)]
+    for teams in (1, 2, 5):
+        tr, red = S.run_region(prog, teams, S.Config(workers=2, schedule="random", seed=teams))
+        yr = R.fma_chain(x, [], [2.0**-50, 2.0**40])
+        assert all(t.error is None for t in tr)
+        assert np.array_equal(y, yr) and R.fixed75_sum(yr) is None
+        assert red == [math.fsum(yr)] == [float(sum(Fraction(float(v)) for v in yr))]
 
 
 def brute_programs(depth):
@@ -311,7 +320,7 @@ def test_sim_stack_brute_force_properties():
                     expect_err = None
                     for op in prog:
                         if isinstance(op, S.Push):
-                            size = -(-op.nbytes // 16) * 16
+                            size = -(-op.nbytes // 8) * 8
                             fits_l = size <= T and sp["lds"] + size <= C
                             fits_h = sp["hbm"] + size <= H
                             if not (fits_l or fits_h):

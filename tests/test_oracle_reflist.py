@@ -52,7 +52,7 @@ def test_list_publish_matches_plain_definition(ni, nf, alen):
         space, off, entries = t.lists[0]
         assert entries == nrefs
         assert space == ("ctl" if nrefs <= 20 else "hbm")
-        assert t.placements == [("lds", 0, S.round_up(size, 16))]   # the list frame is not a push
+        assert t.placements == [("lds", 0, S.round_up(size, 8))]    # the list frame is not a push
 
 
 def test_list_spanning_frames_and_spaces():
