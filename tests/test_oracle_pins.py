@@ -263,6 +263,8 @@ def test_sim_runtime_errors():
     cases = [
         ([S.Push(24, init), pub], "LIVE"),
         ([S.Push(24, init), S.Push(8), S.Pop(0), S.Pop(1)], "ORDER"),
+        # a pop with no live frame has nothing to release: the stack of
+        # section 5.3.1 underflows (not a state error of a live frame)
         ([S.Pop(0)], "UNDERFLOW"),
         ([S.Push(24, init), S.Pop(0), S.Pop(0)], "UNDERFLOW"),
         ([S.Push(24, init), S.Pop(0), pub], "STATE"),

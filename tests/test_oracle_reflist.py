@@ -114,6 +114,8 @@ def test_bad_references():
         ([S.Push(size, init), S.PublishList(refs[:-1], "fma_chain_refs", loop), S.Pop(0)], "INVAL"),
         ([S.Push(size, init), S.PublishList([(0, 0), (0, 36), (0, 40), (0, 28)], "fma_chain_refs", loop),
           S.Pop(0)], "INVAL"),                                   # fp64 not 8-byte aligned
+    # (section 5.3.1 keeps the shared stack's variables 8-byte aligned, so a
+    # reference to an fp64 variable is to an 8-byte boundary)
         ([S.Push(size, init), S.PublishList(refs, "fma_chain", loop), S.Pop(0)], "INVAL"),
     ]
     for prog, code in cases:
