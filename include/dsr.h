@@ -84,11 +84,18 @@ extern "C" {
  * DSR_BODY_GATHER       frame: A int32 arrays of `len` elements back to back.
  *     out (int32[n]): out[i] = sum_j arr_j[i mod len] + i (32-bit wrap).
  *
- * DSR_BODY_GATHER_NESTED  as DSR_BODY_GATHER, run as two nested parallel
- *     levels: each worker wave is a member of the outer level; it pushes a
- *     16-byte inner frame {lo, hi, stride, outer frame} on its own LDS
- *     sub-stack and hands it to its four 16-lane groups (the inner level),
- *     then pops it (section 3.1.2 nesting; section 7 worker-level sharing).
+ * DSR_BODY_GATHER_NESTED  as DSR_BODY_GATHER, run as `depth` (2 or 3)
+ *     nested parallel levels (section 3.1.2 nesting; section 7 sharing at
+ *     worker level).  Each participating wave is a member of the first
+ *     level and takes a contiguous piece of the team's range; it pushes a
+ *     16-byte frame {lo, hi, team frame's space, offset} on its own member
+ *     stack and forks its inner team, four 16-lane groups, which take
+ *     pieces of [lo, hi).  At depth 3 each group pushes a frame of the same
+ *     shape, naming the wave's frame, on its own lane-group stack for four
+ *     4-lane groups.  The innermost lanes reach the arrays by following the
+ *     references.  Member stacks are on chip (64 B per wave, 16 B per lane
+ *     group) with a global part (256 B, 64 B) taken when the on-chip part
+ *     is full or DSR_F_NESTED_GLOBAL is set.
  *
  * DSR_BODY_FMA_CHAIN_REFS  the DSR_BODY_FMA_CHAIN loop, published with
  *     dsr_publish_list: no frame layout, a list of references instead
@@ -109,6 +116,9 @@ extern "C" {
 #define DSR_F_GLOBAL_LISTS 4u  /* every published reference list goes to the
                                   HBM stack, however short (the global list of
                                   section 5.2, for comparison)                */
+#define DSR_F_NESTED_GLOBAL 8u /* nested members' frames skip the on-chip part
+                                  of their stacks (section 7's global stack,
+                                  as when the on-chip part is exhausted)     */
 
 typedef struct dsr_config {
     uint32_t wg_size;            /* threads per team: multiple of 64 in [64, 1024] */
@@ -140,6 +150,8 @@ typedef struct dsr_loop {
                           (1..99; 0 = 25)                                        */
     uint32_t block;    /* DYNAMIC_TAIL: iterations per claim (multiple of 128,
                           at most 65536; 0 = 1024)                               */
+    uint32_t depth;    /* GATHER_NESTED: parallel levels, 2 or 3 (0 = 2)        */
+    uint32_t pad;
 } dsr_loop;
 
 /* Loop schedules.
@@ -270,8 +282,12 @@ int dsr_region_reduction(dsr_region *r, int32_t index, int64_t *i64, double *f64
  *   [89 .. 91]            last reference list published: where (3 on chip,
  *                         1 HBM list frame), its offset, its entries (0: none)
  *   [96 + 2w, 97 + 2w]    low words of the wall clock when wave w started
- *                         and finished its share of the last body it ran   */
-#define DSR_TRACE_WORDS 128
+ *                         and finished its share of the last body it ran
+ *   [128 + 8m .. 135 + 8m] nested member m (last nested body): its frame's
+ *                         placement (space << 24 | offset; space 4 on chip,
+ *                         5 global), its lane groups' frames (depth 3), a
+ *                         pop-order error flag, nested pushes by the wave   */
+#define DSR_TRACE_WORDS 256
 int dsr_region_trace(dsr_region *r, int32_t team, uint32_t *buf, uint32_t n);
 
 /* Duration of the last launch's kernel in milliseconds, from HIP events

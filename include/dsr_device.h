@@ -28,8 +28,16 @@
  *
  * LDS layout of a team (dynamic shared memory):
  *   [header 64 B][frame table 16 x 16 B][reference list 20 x 8 B]
- *   [per-wave reduction slots nw x 32 B][per-wave sub-stacks nw x DSR_SUB_BYTES]
+ *   [per-wave reduction slots nw x 32 B][nested area: nw x DSR_NEST_LDS_WAVE]
  *   [stack: lds_cap bytes]
+ * The nested area holds the on-chip part of every nested member's stack
+ * (section 7's sharing at worker level): with P participating waves,
+ * wave m's stack at m * DSR_NEST_WAVE_LDS, then the stacks of lane group g
+ * of wave m at P * DSR_NEST_WAVE_LDS + (m * DSR_NEST_GROUPS + g) *
+ * DSR_NEST_GROUP_LDS, and, after room for every wave's stacks, each wave's
+ * descriptors (the published frame of the wave and of each of its lane
+ * groups).  The global-memory part of the member stacks is a separate
+ * per-team slot, laid out the same way with the _HBM sizes.
  * The reference list is the on-chip list of section 5.2: a published list
  * of up to DSR_REF_LIST references lives there, a longer one in a list
  * frame on the HBM stack.
@@ -42,14 +50,26 @@
 
 #define DSR_MAX_FRAMES 16
 #define DSR_MAX_WAVES 16
-#define DSR_SUB_BYTES 64u
+#define DSR_NEST_GROUPS 4u       /* inner members per member, at each nested level */
+#define DSR_NEST_FRAME 16u       /* a nested frame: {lo, hi, parent space, parent offset} */
+#define DSR_NEST_WAVE_LDS 64u    /* on-chip part of a wave's member stack        */
+#define DSR_NEST_GROUP_LDS 16u   /* on-chip part of a lane group's member stack  */
+#define DSR_NEST_WAVE_HBM 256u   /* global-memory part of a wave's member stack  */
+#define DSR_NEST_GROUP_HBM 64u   /* global-memory part of a lane group's stack   */
+#define DSR_NEST_DESC 48u        /* per wave: its descriptor + one per lane group */
+/* nested area of one wave (on chip) and of one team per wave (global) */
+#define DSR_NEST_LDS_WAVE (DSR_NEST_WAVE_LDS + DSR_NEST_GROUPS * DSR_NEST_GROUP_LDS + DSR_NEST_DESC)
+#define DSR_NEST_HBM_WAVE (DSR_NEST_WAVE_HBM + DSR_NEST_GROUPS * DSR_NEST_GROUP_HBM)
 #define DSR_ALIGN 16u
 #define DSR_REF_LIST 20u        /* references the on-chip list holds (8 B each) */
 
 namespace dsr {
 
-/* SPACE_LIST names the on-chip reference list (a published list only). */
-enum : uint32_t { SPACE_LDS = 0, SPACE_HBM = 1, SPACE_NONE = 2, SPACE_LIST = 3 };
+/* SPACE_LIST names the on-chip reference list (a published list only);
+ * SPACE_NEST_LDS / SPACE_NEST_HBM the on-chip and global parts of the
+ * nested members' stacks. */
+enum : uint32_t { SPACE_LDS = 0, SPACE_HBM = 1, SPACE_NONE = 2, SPACE_LIST = 3, SPACE_NEST_LDS = 4,
+                  SPACE_NEST_HBM = 5 };
 
 struct frame_t {
     uint32_t space;
@@ -79,7 +99,7 @@ struct cb_header {
 /* Bytes of control block for a team of nw waves. */
 __host__ __device__ constexpr uint32_t cb_bytes(uint32_t nw)
 {
-    return 64u + DSR_MAX_FRAMES * 16u + DSR_REF_LIST * 8u + nw * 32u + nw * DSR_SUB_BYTES;
+    return 64u + DSR_MAX_FRAMES * 16u + DSR_REF_LIST * 8u + nw * 32u + nw * DSR_NEST_LDS_WAVE;
 }
 
 struct team_t {
@@ -92,6 +112,8 @@ struct team_t {
     uint32_t nw;         /* waves in the team                              */
     uint32_t wave;       /* this wave (uniform)                            */
     uint32_t lane;
+    uint8_t *nest_hbm;   /* this team's slot of the nested members' global stacks */
+    uint32_t nest_global; /* 1: nested frames skip the on-chip stacks      */
 };
 
 __device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -111,9 +133,17 @@ __device__ inline uint64_t *red_slot(const team_t &T, uint32_t w)
 {
     return (uint64_t *)(T.lds + 64 + DSR_MAX_FRAMES * 16 + DSR_REF_LIST * 8 + w * 32);
 }
-__device__ inline uint8_t *sub_stack(const team_t &T, uint32_t w)
+/* Base of the team's nested area (on chip). */
+__device__ inline uint8_t *nest_lds(const team_t &T)
 {
-    return T.lds + 64 + DSR_MAX_FRAMES * 16 + DSR_REF_LIST * 8 + T.nw * 32 + w * DSR_SUB_BYTES;
+    return T.lds + 64 + DSR_MAX_FRAMES * 16 + DSR_REF_LIST * 8 + T.nw * 32;
+}
+/* Wave w's descriptor words: [0..1] its published nested frame, then
+ * [2 + 2g .. 3 + 2g] the frame published by its lane group g. */
+__device__ inline uint32_t *nest_desc(const team_t &T, uint32_t w)
+{
+    return (uint32_t *)(nest_lds(T) + T.nw * (DSR_NEST_WAVE_LDS + DSR_NEST_GROUPS * DSR_NEST_GROUP_LDS) +
+                        w * DSR_NEST_DESC);
 }
 
 /* ~__kmpc_kernel_init.  Called by every thread of the team; the master
@@ -132,6 +162,8 @@ __device__ inline team_t team_init(uint8_t *lds, uint32_t nw, uint32_t lds_cap,
     T.hbm_cap = hbm_cap;
     T.wave = uniform(threadIdx.x >> 6);
     T.lane = threadIdx.x & 63u;
+    T.nest_hbm = nullptr;
+    T.nest_global = 0;
     if (T.wave == nw - 1 && T.lane == 0) {
         cb_header *h = header(T);
         h->body = 0;
@@ -254,6 +286,56 @@ __device__ inline void end_parallel(team_t &T, uint64_t w0, uint64_t w1, uint64_
 /* Frame address in LDS or in the team's HBM slot. */
 __device__ inline uint8_t *frame_lds(const team_t &T, frame_t f) { return T.stack_lds + f.off; }
 __device__ inline uint8_t *frame_hbm(const team_t &T, frame_t f) { return T.stack_hbm + f.off; }
+
+/* ---- nested levels (section 3.1.2 nesting; section 7 sharing at worker
+ * level): a member of a parallel level is the master of an inner team.  It
+ * pushes a frame on its own member stack, publishes it to its inner members
+ * and pops it when they have joined.  A member stack has an on-chip part in
+ * the team's nested area and a global-memory part in the team's nested
+ * slot (the runtime-managed global stack of section 7, taken when the
+ * on-chip part is exhausted).  The member's lanes hold the stack pointers
+ * in registers; only the member's leader lane writes the frames. */
+struct mstack_t {
+    uint32_t lds_base, lds_cap;    /* offsets in the nested area              */
+    uint32_t hbm_base, hbm_cap;    /* offsets in the team's nested slot       */
+    uint32_t sp_lds, sp_hbm;
+};
+
+__device__ inline mstack_t mstack(uint32_t lds_base, uint32_t lds_cap, uint32_t hbm_base, uint32_t hbm_cap)
+{
+    return mstack_t{lds_base, lds_cap, hbm_base, hbm_cap, 0u, 0u};
+}
+
+/* Place a nested frame: the on-chip part if it fits, else the global part,
+ * else SPACE_NONE (nothing allocated). */
+__device__ inline frame_t mpush(mstack_t &S, uint32_t nbytes, bool global_only)
+{
+    const uint32_t size = (nbytes + DSR_ALIGN - 1) & ~(DSR_ALIGN - 1);
+    frame_t f;
+    f.size = size;
+    if (!global_only && size <= S.lds_cap - S.sp_lds) {
+        f.space = SPACE_NEST_LDS; f.off = S.lds_base + S.sp_lds; S.sp_lds += size;
+    } else if (size <= S.hbm_cap - S.sp_hbm) {
+        f.space = SPACE_NEST_HBM; f.off = S.hbm_base + S.sp_hbm; S.sp_hbm += size;
+    } else {
+        f.space = SPACE_NONE; f.off = 0;
+    }
+    return f;
+}
+
+/* Pop the member stack's top frame; false if f is not the top. */
+__device__ inline bool mpop(mstack_t &S, frame_t f)
+{
+    if (f.space == SPACE_NEST_LDS && f.off + f.size == S.lds_base + S.sp_lds) { S.sp_lds -= f.size; return true; }
+    if (f.space == SPACE_NEST_HBM && f.off + f.size == S.hbm_base + S.sp_hbm) { S.sp_hbm -= f.size; return true; }
+    return false;
+}
+
+/* Address of (space, offset) in the nested stacks. */
+__device__ inline uint32_t *nest_addr(const team_t &T, uint32_t space, uint32_t off)
+{
+    return (uint32_t *)(space == SPACE_NEST_LDS ? nest_lds(T) + off : T.nest_hbm + off);
+}
 
 /* Typed address of the shared variable `off` bytes into frame f, in
  * whichever space the frame lives (section 5.1: workers reach the master's

@@ -35,6 +35,7 @@ struct dsr_ctx {
     uint32_t lds_bytes;         /* dynamic LDS per team                     */
     uint32_t threshold;
     uint8_t *hbm;
+    uint8_t *nest;              /* nested members' global stacks, DSR_NEST_SLOT per team */
 };
 
 struct dsr_region {
@@ -93,7 +94,7 @@ extern "C" int dsr_init(dsr_ctx **out, const dsr_config *cfg, int device)
     if (c.max_teams == 0) return DSR_E_INVAL;
     if (c.hbm_slab_bytes > 0xFFFFFFF0ull || (c.hbm_slab_bytes & 15u)) return DSR_E_INVAL;
     if (c.lds_slab_bytes & 15u) return DSR_E_INVAL;
-    if (c.flags & ~(DSR_F_TRACE | DSR_F_TIMING | DSR_F_GLOBAL_LISTS)) return DSR_E_INVAL;
+    if (c.flags & ~(DSR_F_TRACE | DSR_F_TIMING | DSR_F_GLOBAL_LISTS | DSR_F_NESTED_GLOBAL)) return DSR_E_INVAL;
     const uint32_t nw = c.wg_size / 64;
     const uint64_t lds = (uint64_t)dsr::cb_bytes(nw) + c.lds_slab_bytes;
     uint32_t lds_max = kDefaultLdsPerWg;
@@ -116,11 +117,17 @@ extern "C" int dsr_init(dsr_ctx **out, const dsr_config *cfg, int device)
     ctx->lds_bytes = (uint32_t)lds;
     ctx->threshold = c.overflow_threshold ? c.overflow_threshold : 0xFFFFFFFFu;
     ctx->hbm = nullptr;
+    ctx->nest = nullptr;
     if (device >= 0) {
         if (hipSetDevice(device) != hipSuccess) { delete ctx; return DSR_E_HIP; }
         const uint64_t bytes = c.hbm_slab_bytes * (uint64_t)c.max_teams;
         if (bytes) {
             if (hipMalloc((void **)&ctx->hbm, bytes) != hipSuccess) { delete ctx; return DSR_E_NOMEM; }
+        }
+        if (hipMalloc((void **)&ctx->nest, (uint64_t)DSR_NEST_SLOT * c.max_teams) != hipSuccess) {
+            if (ctx->hbm) hipFree(ctx->hbm);
+            delete ctx;
+            return DSR_E_NOMEM;
         }
     }
     *out = ctx;
@@ -130,10 +137,9 @@ extern "C" int dsr_init(dsr_ctx **out, const dsr_config *cfg, int device)
 extern "C" int dsr_destroy(dsr_ctx *ctx)
 {
     if (!ctx) return DSR_E_INVAL;
-    if (ctx->hbm) {
-        hipDeviceSynchronize();
-        hipFree(ctx->hbm);
-    }
+    if (ctx->hbm || ctx->nest) hipDeviceSynchronize();
+    if (ctx->hbm) hipFree(ctx->hbm);
+    if (ctx->nest) hipFree(ctx->nest);
     delete ctx;
     return DSR_OK;
 }
@@ -253,6 +259,7 @@ static int prepare_loop(const dsr_region *r, const dsr_loop &L, const int32_t *f
     dl.len = L.len;
     dl.schedule = L.schedule;
     dl.block = block;
+    dl.depth = L.depth;
     dl.dyn_start = dyn_start;
     *out = dl;
     return DSR_OK;
@@ -299,7 +306,11 @@ extern "C" int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr
     }
     case DSR_BODY_GATHER:
     case DSR_BODY_GATHER_NESTED:
-        if (body == DSR_BODY_GATHER_NESTED && L.schedule != DSR_SCHED_STATIC) return DSR_E_INVAL;
+        if (body == DSR_BODY_GATHER_NESTED) {
+            if (L.schedule != DSR_SCHED_STATIC) return DSR_E_INVAL;
+            if (L.depth != 0 && L.depth != 2 && L.depth != 3) return DSR_E_INVAL;
+            dl.depth = L.depth ? L.depth : 2;
+        }
         if (L.arrays < 1 || L.arrays > 16 || L.len < 1) return DSR_E_INVAL;
         if ((uint64_t)nb < 4ull * L.arrays * L.len) return DSR_E_INVAL;
         break;
@@ -466,6 +477,8 @@ static dsr_dconfig make_dconfig(const dsr_ctx *c, uint32_t wg, uint32_t lds_slab
     C.master_joins = ((joins && C.nw <= 8) || C.nw == 1) ? 1u : 0u;
     C.trace = trace;
     C.global_lists = (c->cfg.flags & DSR_F_GLOBAL_LISTS) ? 1u : 0u;
+    C.nest_global = (c->cfg.flags & DSR_F_NESTED_GLOBAL) ? 1u : 0u;
+    C.nest_base = c->nest;
     return C;
 }
 

@@ -37,7 +37,7 @@ struct dsr_dloop {
     const void *in;
     void *out;
     uint32_t ni, nf, alen, arrays;
-    uint32_t len, schedule, block, pad;
+    uint32_t len, schedule, block, depth;   /* depth: nested levels (nested body) */
     uint64_t dyn_start;    /* first iteration of the dynamic tail (= n if none) */
 };
 
@@ -143,8 +143,14 @@ struct dsr_dconfig {
     uint32_t trace;
     uint32_t serve;        /* served form: per-item program copy after the stack */
     uint32_t global_lists; /* every reference list goes to the HBM stack      */
-    uint32_t pad;
+    uint32_t nest_global;  /* nested frames skip the on-chip member stacks     */
+    uint8_t *nest_base;    /* nested members' global stacks: one slot of
+                              DSR_NEST_SLOT bytes per workgroup               */
 };
+
+/* Global part of the nested member stacks per workgroup: room for the
+ * largest team (16 waves) whatever the launch's workgroup size. */
+#define DSR_NEST_SLOT (16u * DSR_NEST_HBM_WAVE)
 
 /* Compiled instances of the region kernel: (tag, largest workgroup, variant).
  * The build compiles dsr_kernels.hip once per entry, in parallel, and

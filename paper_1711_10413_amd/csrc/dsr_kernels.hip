@@ -769,8 +769,9 @@ __device__ __forceinline__ i32x4 gather4(AP arr, uint32_t len, uint32_t na, uint
     return s;
 }
 
-/* Vectors [v0, v1) of 4 elements, visited v0 + k*stride; len % 4 == 0. */
-template <int NA, class AP>
+/* Vectors [v0, v1) of 4 elements, visited v0 + k*stride; len % 4 == 0.
+ * BATCH4: four vectors at a time (false where registers are scarce). */
+template <int NA, class AP, bool BATCH4 = true>
 __device__ __forceinline__ void gather_vectors(AP arr, const dsr_dloop &L, uint64_t v0, uint64_t v1,
                                                uint64_t stride)
 {
@@ -780,7 +781,7 @@ __device__ __forceinline__ void gather_vectors(AP arr, const dsr_dloop &L, uint6
     const uint32_t step = (uint32_t)((stride * 4) % len);
     uint64_t v = v0;
     /* four vectors at a time, their array reads (LDS or global) all in flight */
-    for (; v + 3 * stride < v1; v += 4 * stride) {
+    for (; BATCH4 && v + 3 * stride < v1; v += 4 * stride) {
         const uint32_t i1 = mod_step(idx, step, len), i2 = mod_step(i1, step, len), i3 = mod_step(i2, step, len);
         i32x4 s[4] = {gather4<NA>(arr, len, L.arrays, idx), gather4<NA>(arr, len, L.arrays, i1),
                       gather4<NA>(arr, len, L.arrays, i2), gather4<NA>(arr, len, L.arrays, i3)};
@@ -827,42 +828,142 @@ __device__ __forceinline__ void gather_span(AP arr, const dsr_dloop &L, span_t s
     gather_scalar(arr, L, sp.lo + 4 * nv + sp.p, sp.hi, sp.P);
 }
 
-/* Nested level: the outer member (this wave) pushes an inner frame on its
- * own sub-stack and hands it to its four 16-lane groups. */
-template <int NA, class AP>
-__device__ __forceinline__ void body_gather_nested(team_t &T, AP arr, frame_t outer, const dsr_dloop &L,
-                                                   span_t sp, uint32_t member, uint32_t members,
-                                                   uint32_t &inner_pushes)
+/* ---- nested levels ----------------------------------------------------------
+ * Part k of [lo, hi) cut into `parts` contiguous pieces whose lengths are
+ * multiples of `gran` elements (4 keeps every piece on 16-byte vectors). */
+__device__ __forceinline__ void split_range(uint64_t lo, uint64_t hi, uint32_t parts, uint32_t k, uint32_t gran,
+                                            uint64_t &a, uint64_t &b)
 {
+    const uint64_t n = hi > lo ? hi - lo : 0;
+    uint64_t per = (n + parts - 1) / parts;
+    per = (per + gran - 1) / gran * gran;
+    a = min(hi, lo + (uint64_t)k * per);
+    b = min(hi, a + per);
+}
+
+/* The innermost members' loop: elements [a, b) over G lanes (q = this
+ * lane's index), on 16-byte vectors when `vec` (a is then a multiple of 4). */
+template <int NA, bool BATCH4, class AP>
+__device__ __forceinline__ void gather_leaf(AP arr, const dsr_dloop &L, uint64_t a, uint64_t b, uint32_t q,
+                                            uint32_t G, bool vec)
+{
+    if (vec) {
+        const uint64_t v1 = b >> 2;
+        gather_vectors<NA, AP, BATCH4>(arr, L, (a >> 2) + q, v1, G);
+        gather_scalar(arr, L, (v1 << 2) + q, b, G);
+    } else {
+        gather_scalar(arr, L, a + q, b, G);
+    }
+}
+
+/* The gather through a reference to the team's frame (space, offset). */
+template <int NA, bool BATCH4>
+__device__ __forceinline__ void gather_leaf_at(const team_t &T, uint32_t space, uint32_t off, const dsr_dloop &L,
+                                               uint64_t a, uint64_t b, uint32_t q, uint32_t G, bool vec)
+{
+    if (space == SPACE_LDS)
+        gather_leaf<NA, BATCH4>((const LDSQ int32_t *)(dsr_lds + cb_bytes(T.nw) + off), L, a, b, q, G, vec);
+    else
+        gather_leaf<NA, BATCH4>((const GLB int32_t *)(T.stack_hbm + off), L, a, b, q, G, vec);
+}
+
+/* A nested fork or join inside one wave: the leader lanes' frame and
+ * descriptor writes (LDS, or the global part of a member stack) become
+ * visible to the wave's other lanes.  Workgroup scope covers both memories
+ * (the wave's own CU). */
+__device__ __forceinline__ void nest_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ uint32_t pack_place(frame_t f) { return (f.space << 24) | f.off; }
+
+/* Nested levels below the team's fork (section 3.1.2; section 7's sharing
+ * at worker level).  Level 1: this wave is member `member` of `members`
+ * and takes its piece of the team's range.  It pushes the frame {lo, hi,
+ * team frame's space, offset} on its own member stack, publishes it in its
+ * descriptor and forks its inner team, the four 16-lane groups.  Level 2:
+ * each group reads the descriptor, then the frame, and takes its piece.  At
+ * depth 2 its lanes gather through the team frame the frame names.  At
+ * depth 3 each group's leader lane pushes a frame {lo, hi, the wave frame's
+ * space, offset} on the group's own member stack and forks the group's
+ * inner team, four 4-lane groups, which reach the team frame by following
+ * the two references.  Frames are popped in LIFO order after each inner
+ * team joins.  A member stack's frame goes to its on-chip part, or to its
+ * global part when the on-chip part is full or `nest_global` is set; each
+ * global part holds several nested frames, so no nested push fails. */
+template <int NA, bool BATCH4>
+__device__ __forceinline__ void body_gather_nested(team_t &T, frame_t outer, const dsr_dloop &L, span_t sp,
+                                                   uint32_t member, uint32_t members, uint32_t &inner_pushes,
+                                                   uint32_t *tr)
+{
+    static_assert(DSR_NEST_WAVE_HBM >= DSR_NEST_FRAME && DSR_NEST_GROUP_HBM >= DSR_NEST_FRAME,
+                  "a global part holds at least one nested frame");
+    const uint32_t depth = uniform(L.depth);
     const bool vec = !((L.len & 3u) || (sp.lo & 3u));
-    const uint64_t units = vec ? ((sp.hi - sp.lo) >> 2) : (sp.hi - sp.lo);
-    const uint64_t per = (units + members - 1) / members;
-    const uint64_t ulo = min(units, (uint64_t)member * per), uhi = min(units, ulo + per);
-    /* push the inner frame {lo, hi, stride, outer frame offset} */
-    uint32_t *inner = (uint32_t *)sub_stack(T, T.wave);
-    if (T.lane == 0) {
-        inner[0] = (uint32_t)ulo;
-        inner[1] = (uint32_t)uhi;
-        inner[2] = 64u;
-        inner[3] = outer.off;
+    const uint32_t gran = vec ? 4u : 1u;
+    const uint32_t lane = T.lane;
+    uint32_t *desc = nest_desc(T, member);
+    /* level 1: this wave's piece and its frame */
+    uint64_t mlo, mhi;
+    split_range(sp.lo, sp.hi, members, member, gran, mlo, mhi);
+    mstack_t ws = mstack(member * DSR_NEST_WAVE_LDS, DSR_NEST_WAVE_LDS, member * DSR_NEST_WAVE_HBM,
+                         DSR_NEST_WAVE_HBM);
+    const frame_t f2 = mpush(ws, DSR_NEST_FRAME, T.nest_global != 0);
+    uint32_t *p2 = nest_addr(T, f2.space, f2.off);
+    if (lane == 0) {
+        p2[0] = (uint32_t)mlo;
+        p2[1] = (uint32_t)mhi;
+        p2[2] = outer.space;
+        p2[3] = outer.off;
+        desc[0] = f2.space;
+        desc[1] = f2.off;
+        if (tr) tr[128 + 8 * member] = pack_place(f2);
     }
     inner_pushes += 1;
-    wave_sync();
-    /* inner members: group g = lane / 16 reads the inner frame */
-    const uint32_t ilo = uniform(inner[0]), ihi = uniform(inner[1]), istride = uniform(inner[2]);
-    const uint32_t g = T.lane >> 4, l = T.lane & 15u;
-    if (vec) {
-        const uint64_t base = sp.lo >> 2;
-        gather_vectors<NA>(arr, L, base + ilo + g * 16 + l, base + ihi, istride);
-        if (member == members - 1) {
-            const uint64_t tail = sp.lo + 4 * units;
-            gather_scalar(arr, L, tail + T.lane, sp.hi, 64);
-        }
+    nest_sync();
+    /* level 2: lane group g reads the published frame */
+    const uint32_t g = lane >> 4, l = lane & 15u;
+    const uint32_t d2s = desc[0], d2o = desc[1];
+    const uint32_t *q2 = nest_addr(T, d2s, d2o);
+    const uint32_t vlo = q2[0], vhi = q2[1], osp = q2[2], ooff = q2[3];
+    uint64_t glo, ghi;
+    split_range(vlo, vhi, DSR_NEST_GROUPS, g, gran, glo, ghi);
+    if (depth == 2) {
+        gather_leaf_at<NA, BATCH4>(T, osp, ooff, L, glo, ghi, l, 16u, vec);
     } else {
-        gather_scalar(arr, L, sp.lo + ilo + g * 16 + l, sp.lo + ihi, istride);
+        const uint32_t k = member * DSR_NEST_GROUPS + g;
+        mstack_t gs = mstack(members * DSR_NEST_WAVE_LDS + k * DSR_NEST_GROUP_LDS, DSR_NEST_GROUP_LDS,
+                             members * DSR_NEST_WAVE_HBM + k * DSR_NEST_GROUP_HBM, DSR_NEST_GROUP_HBM);
+        const frame_t f3 = mpush(gs, DSR_NEST_FRAME, T.nest_global != 0);
+        uint32_t *p3 = nest_addr(T, f3.space, f3.off);
+        if (l == 0) {
+            p3[0] = (uint32_t)glo;
+            p3[1] = (uint32_t)ghi;
+            p3[2] = d2s;
+            p3[3] = d2o;
+            desc[2 + 2 * g] = f3.space;
+            desc[3 + 2 * g] = f3.off;
+            if (tr) tr[129 + 8 * member + g] = pack_place(f3);
+        }
+        inner_pushes += DSR_NEST_GROUPS;
+        nest_sync();
+        /* level 3: 4-lane group s of group g */
+        const uint32_t s = l >> 2, q = l & 3u;
+        const uint32_t *q3 = nest_addr(T, desc[2 + 2 * g], desc[3 + 2 * g]);
+        const uint32_t slo = q3[0], shi = q3[1];
+        const uint32_t *pp = nest_addr(T, q3[2], q3[3]);      /* the wave's frame */
+        uint64_t a, b;
+        split_range(slo, shi, DSR_NEST_GROUPS, s, gran, a, b);
+        gather_leaf_at<NA, BATCH4>(T, pp[2], pp[3], L, a, b, q, 4u, vec);
+        nest_sync();                                            /* inner join */
+        if (!mpop(gs, f3) && tr) tr[133 + 8 * member] = 1;
     }
-    /* pop: the inner frame dies with the outer member's body */
-    wave_sync();
+    nest_sync();                                                /* inner join */
+    if (!mpop(ws, f2) && tr && lane == 0) tr[133 + 8 * member] = 1;
+    if (tr && lane == 0) tr[134 + 8 * member] = inner_pushes;
 }
 
 /* Cross-team traffic (partials, arrival counters, results) uses
@@ -904,7 +1005,7 @@ __device__ __forceinline__ const uint8_t *frame_ptr(const team_t &T, frame_t f)
 template <int VARIANT>
 __device__ __forceinline__ void run_body(team_t &T, uint32_t body, frame_t f, const dsr_dloop &L, span_t sp,
                                          lane_acc &A, uint32_t *claim, uint32_t member,
-                                         uint32_t members, uint32_t &inner_pushes)
+                                         uint32_t members, uint32_t &inner_pushes, uint32_t *tr)
 {
     const uint32_t lane = T.lane;
     switch (body) {
@@ -994,24 +1095,12 @@ __device__ __forceinline__ void run_body(team_t &T, uint32_t body, frame_t f, co
         break;
     }
     case DSR_BODY_GATHER_NESTED: {
-        if (f.space == SPACE_LDS) {
-            const LDSQ int32_t *arr = (const LDSQ int32_t *)(dsr_lds + cb_bytes(T.nw) + f.off);
-            switch (L.arrays) {
-            case 1: body_gather_nested<1>(T, arr, f, L, sp, member, members, inner_pushes); break;
-            case 2: body_gather_nested<2>(T, arr, f, L, sp, member, members, inner_pushes); break;
-            case 3: body_gather_nested<3>(T, arr, f, L, sp, member, members, inner_pushes); break;
-            case 4: body_gather_nested<4>(T, arr, f, L, sp, member, members, inner_pushes); break;
-            default: body_gather_nested<0>(T, arr, f, L, sp, member, members, inner_pushes); break;
-            }
-        } else {
-            const GLB int32_t *arr = (const GLB int32_t *)frame_hbm(T, f);
-            switch (L.arrays) {
-            case 1: body_gather_nested<1>(T, arr, f, L, sp, member, members, inner_pushes); break;
-            case 2: body_gather_nested<2>(T, arr, f, L, sp, member, members, inner_pushes); break;
-            case 3: body_gather_nested<3>(T, arr, f, L, sp, member, members, inner_pushes); break;
-            case 4: body_gather_nested<4>(T, arr, f, L, sp, member, members, inner_pushes); break;
-            default: body_gather_nested<0>(T, arr, f, L, sp, member, members, inner_pushes); break;
-            }
+        switch (L.arrays) {
+        case 1: body_gather_nested<1, (VARIANT >= 0)>(T, f, L, sp, member, members, inner_pushes, tr); break;
+        case 2: body_gather_nested<2, (VARIANT >= 0)>(T, f, L, sp, member, members, inner_pushes, tr); break;
+        case 3: body_gather_nested<3, (VARIANT >= 0)>(T, f, L, sp, member, members, inner_pushes, tr); break;
+        case 4: body_gather_nested<4, (VARIANT >= 0)>(T, f, L, sp, member, members, inner_pushes, tr); break;
+        default: body_gather_nested<0, (VARIANT >= 0)>(T, f, L, sp, member, members, inner_pushes, tr); break;
         }
         break;
     }
@@ -1042,7 +1131,7 @@ __device__ __forceinline__ void participate(team_t &T, const dsr_dregion &R, con
     uint32_t *tr = (C.trace && R.trace) ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
     if (tr && T.lane == 0) tr[96 + 2 * T.wave] = (uint32_t)wall_clock64();
     run_body<VARIANT>(T, body, f, L, team_span(L, team, T.wave * 64 + T.lane, nwork * 64), A,
-                      &R.result->claim[loop], T.wave, nwork, inner_pushes);
+                      &R.result->claim[loop], T.wave, nwork, inner_pushes, tr);
     if (tr && T.lane == 0) tr[97 + 2 * T.wave] = (uint32_t)wall_clock64();
     /* served form: the request completes while the kernel keeps running,
      * so this wave's output stores must have reached L2 before the join
@@ -1575,6 +1664,8 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
 {
     team_t T = team_init(dsr_lds, C.nw, C.lds_cap, C.threshold,
                          C.hbm_base + (uint64_t)blockIdx.x * C.hbm_slot_bytes, (uint32_t)C.hbm_slot_bytes);
+    T.nest_hbm = C.nest_base + (uint64_t)blockIdx.x * DSR_NEST_SLOT;
+    T.nest_global = C.nest_global;
     const bool single = LP.items == nullptr;
     uint32_t barriers = 0, inner_pushes = 0;
     if (LP.published && T.wave == C.nw - 1 && T.lane == 0) {

@@ -44,7 +44,9 @@ DSR_SCHED_DYNAMIC_TAIL = 1
 DSR_F_TRACE = 1
 DSR_F_TIMING = 2
 DSR_F_GLOBAL_LISTS = 4
-DSR_TRACE_WORDS = 128
+DSR_F_NESTED_GLOBAL = 8
+DSR_TRACE_WORDS = 256
+NEST_SPACES = {4: "nlds", 5: "nhbm"}
 
 # the exported C entry points (include/dsr.h)
 EXPORTS = ("dsr_init", "dsr_destroy", "dsr_region_begin", "dsr_push", "dsr_publish",
@@ -73,7 +75,8 @@ class dsr_loop(C.Structure):
     _fields_ = [("n", C.c_uint64), ("chunk", C.c_uint64), ("in_", C.c_void_p),
                 ("out", C.c_void_p), ("ni", C.c_uint32), ("nf", C.c_uint32),
                 ("alen", C.c_uint32), ("arrays", C.c_uint32), ("len", C.c_uint32),
-                ("schedule", C.c_uint32), ("tail_pct", C.c_uint32), ("block", C.c_uint32)]
+                ("schedule", C.c_uint32), ("tail_pct", C.c_uint32), ("block", C.c_uint32),
+                ("depth", C.c_uint32), ("pad", C.c_uint32)]
 
 
 class dsr_tune(C.Structure):
@@ -259,9 +262,9 @@ def dsr_push(region, nbytes, init=b"", init_stride=0, init_bytes=None):
 
 
 def dsr_publish(region, frame, body, n, inp=0, out=0, chunk=0, ni=0, nf=0, alen=0, arrays=0,
-                length=0, schedule=0, tail_pct=0, block=0):
+                length=0, schedule=0, tail_pct=0, block=0, depth=0):
     L = dsr_loop(n, chunk, inp or None, out or None, ni, nf, alen, arrays, length, schedule,
-                 tail_pct, block)
+                 tail_pct, block, depth)
     return _check(lib().dsr_publish(region, frame, body, C.byref(L)), "dsr_publish")
 
 
@@ -319,7 +322,15 @@ def dsr_region_trace(region, team):
             "t_start": t[82] | (t[83] << 32), "t_end": t[84] | (t[85] << 32),
             "t_team": t[86], "t_program_end": t[87], "t_arrived": t[88],
             "list": (("lds", "hbm", "none", "onchip")[t[89]], t[90], t[91]) if t[91] else None,
-            "wave_loop": [(t[96 + 2 * w], t[97 + 2 * w]) for w in range(16)]}
+            "wave_loop": [(t[96 + 2 * w], t[97 + 2 * w]) for w in range(16)],
+            "nested": [{"frame": _nest_place(t[128 + 8 * m]),
+                        "groups": [_nest_place(t[129 + 8 * m + g]) for g in range(4)],
+                        "pop_error": t[133 + 8 * m], "pushes": t[134 + 8 * m]} for m in range(16)]}
+
+
+def _nest_place(w):
+    """A nested frame's placement word: (space, offset) or None."""
+    return (NEST_SPACES[w >> 24], w & 0xFFFFFF) if (w >> 24) in NEST_SPACES else None
 
 
 def dsr_region_elapsed(region):

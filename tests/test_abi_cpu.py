@@ -39,12 +39,12 @@ def test_bad_configs():
     for kw, code in [({"wg_size": 100}, D.DSR_E_INVAL), ({"wg_size": 2048}, D.DSR_E_INVAL),
                      ({"max_teams": 0}, D.DSR_E_INVAL), ({"lds_slab_bytes": 20}, D.DSR_E_INVAL),
                      ({"lds_slab_bytes": 160 * 1024}, D.DSR_E_LDS),
-                     ({"hbm_slab_bytes": 17}, D.DSR_E_INVAL), ({"flags": 8}, D.DSR_E_INVAL),
-                     ({"flags": 16}, D.DSR_E_INVAL)]:
+                     ({"hbm_slab_bytes": 17}, D.DSR_E_INVAL), ({"flags": 16}, D.DSR_E_INVAL),
+                     ({"flags": 32}, D.DSR_E_INVAL)]:
         with pytest.raises(D.DsrError) as e:
             host_ctx(**kw)
         assert e.value.code == code, kw
-    ctx = host_ctx(lds_slab_bytes=160 * 1024 - 1024)     # fits with a 4-wave control block
+    ctx = host_ctx(lds_slab_bytes=160 * 1024 - 2048)     # fits with a 4-wave control block
     D.dsr_destroy(ctx)
 
 
@@ -204,7 +204,7 @@ def test_publish_list_validation():
             prog.append(S.Pop(0))
         tr, _ = S.run_region(prog, 1)
         assert tr[0].error == code
-    assert D.dsr_control_bytes(256) == 64 + 16 * 16 + 20 * 8 + 4 * 32 + 4 * 64
+    assert D.dsr_control_bytes(256) == 64 + 16 * 16 + 20 * 8 + 4 * 32 + 4 * (64 + 4 * 16 + 48)
     D.dsr_destroy(ctx)
 
 
@@ -233,4 +233,19 @@ def test_list_programs_pass_host_checks(ni, nf, alen, lds, flags):
     D.dsr_pop(r, f1)
     D.dsr_pop(r, f0)
     D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+
+
+def test_nested_depth_is_checked_on_the_host():
+    ctx = host_ctx(lds_slab_bytes=4096, hbm_slab_bytes=4096)
+    for depth, code in ((0, 0), (2, 0), (3, 0), (1, D.DSR_E_INVAL), (4, D.DSR_E_INVAL)):
+        r = D.dsr_region_begin(ctx, 2)
+        f = D.dsr_push(r, 64)
+        try:
+            D.dsr_publish(r, f, D.DSR_BODY_GATHER_NESTED, 100, out=1 << 20, arrays=1, length=16, depth=depth)
+            got = 0
+        except D.DsrError as e:
+            got = e.code
+        assert got == code, depth
+        D.dsr_region_free(r)
     D.dsr_destroy(ctx)
