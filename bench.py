@@ -603,26 +603,64 @@ def run_served(torch, np, D, W, stream, rates, seconds, pool=1000, seed=4, slots
 
 
 # ---- CPU baseline ---------------------------------------------------------------
-def cpu_baseline(W, seconds_target=12.0):
-    """The oracle, single-threaded, on a bounded sample of the sweep: the
-    first 2**21 elements of x for every K (1/8 of each region)."""
+def cpu_baseline(W, runs=5, one_core_elems=1 << 22):
+    """The oracle on the host's cores.  One run computes, for each K of the
+    sweep, y with the oracle's fma chain and its exact 2^-75 fixed-point
+    total (oracle/ref.c), over slices of the range in a pool of threads
+    (the C calls release the interpreter lock); the slices' exact integer
+    totals are added and rounded once (Python's int / int is correctly
+    rounded).  All-core: whole 2^24-element regions on every thread the
+    box gives this process; one core: the first 2^22 elements of each
+    region on one thread, scaled to whole regions.  Medians of `runs`."""
+    import statistics
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import ref as R
-    sample = 1 << 21
-    _, x = W.cfg2_inputs(1, n=sample)
-    passes, t0 = 0, time.perf_counter()
-    while True:
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = max(1, min(ncpu, int(os.environ.get("OMP_NUM_THREADS") or ncpu), 16))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    _, x = W.cfg2_inputs(1, n=N)
+    scal = {K: W.cfg2_inputs(K, n=N, with_x=False)[0] for K in W.CFG2_KS}
+
+    def piece(K, lo, hi):
+        y = R.fma_chain(x[lo:hi], scal[K].s_i32, scal[K].s_f64)
+        return R.fixed75_sum(y)
+
+    def sweep(n, nthreads, pool):
+        step = -(-n // nthreads)
+        out = {}
         for K in W.CFG2_KS:
-            cf, _ = W.cfg2_inputs(K, n=sample, with_x=False)
-            R.exact_sum(R.fma_chain(x, cf.s_i32, cf.s_f64))
-        passes += 1
-        el = time.perf_counter() - t0
-        if el >= seconds_target or passes >= 50:
-            break
-    regions_done = passes * len(W.CFG2_KS) * sample / N
-    return {"value": regions_done / el, "unit": "region instances/s", "cores": 1, "kind": "oracle",
-            "sample": "%d pass(es) of the K sweep over the first 2^21 of 2^24 elements "
-                      "(fma chain + exact sum, C, one thread), %.1f s, scaled to whole "
-                      "regions" % (passes, el)}
+            parts = [pool.submit(piece, K, lo, min(n, lo + step)) for lo in range(0, n, step)]
+            out[K] = sum(p.result() for p in parts) / (1 << 75)
+        return out
+
+    def timed(n, nthreads):
+        secs = []
+        with ThreadPoolExecutor(nthreads) as pool:
+            for _ in range(runs):
+                t0 = time.perf_counter()
+                sweep(n, nthreads, pool)
+                secs.append(time.perf_counter() - t0)
+        return statistics.median(secs)
+
+    t1 = timed(one_core_elems, 1)
+    tn = timed(N, threads)
+    one = len(W.CFG2_KS) * (one_core_elems / N) / t1
+    allc = len(W.CFG2_KS) / tn
+    return {"value": allc, "unit": "region instances/s", "cores": threads, "kind": "oracle",
+            "sample": "the K sweep (7 regions of 2^24 elements: fma chain + exact fixed-point sum, "
+                      "oracle/ref.c): all-core median of %d runs over whole regions on %d threads "
+                      "(%.2f s per run); one-core median of %d runs over the first 2^22 elements of "
+                      "each region, scaled (%.2f s per run)" % (runs, threads, tn, runs, t1),
+            "cpu_model": model, "nproc": ncpu, "one_core_value": one, "all_core_value": allc,
+            "runs": runs}
 
 
 def main():

@@ -1583,8 +1583,14 @@ __device__ __forceinline__ bool wait_item(const dsr_dlaunch &LP, uint32_t it, ui
                     }
                     nap = 0;
                 }
+                /* another workgroup may store a newer time into `last`
+                 * after this wave read its clock and before its load of
+                 * `last` is served: the difference is then negative, which
+                 * means recent work, not idleness (unsigned, it would wrap
+                 * to a huge value and close a busy server) */
                 const uint64_t t_last = __hip_atomic_load(last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (wall_clock64() - t_last > LP.idle_limit) {
+                const int64_t idle = (int64_t)((uint64_t)wall_clock64() - t_last);
+                if (idle > (int64_t)LP.idle_limit) {
                     close_server(LP);
                     continue;
                 }
