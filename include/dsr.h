@@ -298,6 +298,43 @@ int dsr_region_elapsed(dsr_region *r, float *ms);
 /* Release a region's host and device memory (syncs its last launch). */
 int dsr_region_free(dsr_region *r);
 
+/* ---- launch without allocation --------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * dsr_launch_static runs the same region kernel as dsr_launch, but every
+ * device buffer the launch needs -- the region's descriptor, program, loop
+ * descriptors and frame images, its teams' HBM stack slots (cfg.hbm_slab_bytes
+ * each) and, when a nested body is published, their nested members' global
+ * stacks, the cross-team partials and the result block -- lies in one fixed
+ * device workspace of DSR_STATIC_SCRATCH_BYTES that the library holds on
+ * each GPU it runs on until the process ends.  It calls no hipMalloc,
+ * hipFree or other allocating routine: the program is copied in with
+ * hipMemcpyAsync, the result block is cleared by a fill kernel, and the
+ * result is written by a kernel to `result`, a device pointer to one
+ * dsr_result_rec owned by the caller.  The region's context may be
+ * host-only (device < 0: the current device is used) or a device context
+ * (its own slab is not used).  Every call on one GPU uses the same
+ * workspace and leaves its contents behind: calls whose launches overlap
+ * on one GPU (other streams, or other threads) race and must be
+ * serialised by the caller; one stream serialises them.
+ * Errors: DSR_E_INVAL (null argument, or more teams than the context's
+ * max_teams), DSR_E_LIVE (a frame still live), DSR_E_NOMEM (the launch
+ * needs more than DSR_STATIC_SCRATCH_BYTES: teams x hbm_slab_bytes plus
+ * the program and partials; see dsr_static_bytes), DSR_E_HIP.
+ * Asynchronous; the record is complete when `stream` has reached it. */
+#define DSR_STATIC_SCRATCH_BYTES (16u << 20)
+typedef struct dsr_result_rec {
+    int32_t status;           /* DSR_OK, DSR_E_NOMEM or DSR_E_RANGE              */
+    int32_t n_red;            /* reductions recorded (publishes with a reduction) */
+    double f64[8];            /* FMA_CHAIN: correctly rounded sums               */
+    int64_t i64[8];           /* AFFINE_XOR: int64 sums                          */
+    uint64_t fixed[8][3];     /* FMA_CHAIN: exact totals in units of 2^-75       */
+} dsr_result_rec;
+int dsr_launch_static(dsr_region *r, dsr_result_rec *result, void *stream);
+
+/* Workspace bytes dsr_launch_static needs for region r (0 if r is NULL). */
+uint64_t dsr_static_bytes(const dsr_region *r);
+
 /* ---- batched form ---------------------------------------------------------
  * Not in the paper: the batched workload (10,000 region instances in one
  * persistent, graph-captured launch) built on the paper's runtime.

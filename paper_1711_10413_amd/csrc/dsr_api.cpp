@@ -65,6 +65,8 @@ struct dsr_region {
     bool launched;
     dsr_dresult h_result;
     bool have_result;
+    dsr_dregion static_desc;            /* descriptor copied into the workspace by
+                                           dsr_launch_static */
 };
 
 extern "C" const char *dsr_strerror(int code)
@@ -583,6 +585,109 @@ extern "C" int dsr_region_free(dsr_region *r)
     if (r->ev1) hipEventDestroy(r->ev1);
     delete r;
     return DSR_OK;
+}
+
+/* ---- launch without allocation ------------------------------------------------ */
+namespace {
+
+struct static_layout {
+    size_t desc, ops, loops, init, partials, result, hbm, nest, total;
+    bool nested;
+};
+
+size_t up256(size_t v) { return (v + 255u) & ~(size_t)255u; }
+
+/* Where each device buffer of region r goes in the fixed workspace. */
+static_layout static_plan(const dsr_region *r)
+{
+    static_layout L{};
+    L.nested = false;
+    for (const dsr_op &op : r->ops)
+        if (op.kind == DSR_OP_PUBLISH && op.body == DSR_BODY_GATHER_NESTED) L.nested = true;
+    size_t o = 0;
+    L.desc = o;
+    o = up256(o + sizeof(dsr_dregion));
+    L.ops = o;
+    o = up256(o + std::max<size_t>(1, r->ops.size()) * sizeof(dsr_op));
+    L.loops = o;
+    o = up256(o + std::max<size_t>(1, r->loops.size()) * sizeof(dsr_dloop));
+    L.init = o;
+    o = up256(o + std::max<size_t>(16, r->init.size()));
+    L.partials = o;
+    o = up256(o + (size_t)(r->n_red ? r->n_red : 1) * r->teams * DSR_PART_WORDS * sizeof(uint64_t));
+    L.result = o;
+    o = up256(o + sizeof(dsr_dresult));
+    L.hbm = o;
+    o = up256(o + (size_t)r->teams * r->ctx->cfg.hbm_slab_bytes);
+    L.nest = o;
+    if (L.nested) o = up256(o + (size_t)r->teams * DSR_NEST_SLOT);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+extern "C" uint64_t dsr_static_bytes(const dsr_region *r)
+{
+    return r ? (uint64_t)static_plan(r).total : 0;
+}
+
+extern "C" int dsr_launch_static(dsr_region *r, dsr_result_rec *result, void *stream)
+{
+    static_assert(DSR_MAX_RED == 8, "dsr_result_rec holds eight reductions");
+    if (!r || !result) return DSR_E_INVAL;
+    if (!r->live.empty()) return DSR_E_LIVE;
+    dsr_ctx *c = r->ctx;
+    if ((uint64_t)r->teams > c->cfg.max_teams) return DSR_E_INVAL;
+    const static_layout L = static_plan(r);
+    if (L.total > DSR_STATIC_SCRATCH_BYTES) return DSR_E_NOMEM;
+    int dev = c->device;
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return DSR_E_HIP;
+    if (hipSetDevice(dev) != hipSuccess) return DSR_E_HIP;
+    uint8_t *ws = nullptr;
+    int rc = dsr_static_workspace(dev, &ws);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    dsr_dregion &R = r->static_desc;
+    R = dsr_dregion{};
+    R.ops = (const dsr_op *)(ws + L.ops);
+    R.loops = (const dsr_dloop *)(ws + L.loops);
+    R.init = ws + L.init;
+    R.partials = (uint64_t *)(ws + L.partials);
+    R.result = (dsr_dresult *)(ws + L.result);
+    R.trace = nullptr;
+    R.n_ops = (uint32_t)r->ops.size();
+    R.teams = (uint32_t)r->teams;
+    R.n_red = r->n_red;
+    R.red_kind_mask = r->red_kind_mask;
+    R.n_loops = (uint32_t)r->loops.size();
+    if (hipMemcpyAsync(ws + L.desc, &R, sizeof(R), hipMemcpyHostToDevice, s) != hipSuccess) return DSR_E_HIP;
+    if (!r->ops.empty() &&
+        hipMemcpyAsync(ws + L.ops, r->ops.data(), r->ops.size() * sizeof(dsr_op), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+        return DSR_E_HIP;
+    if (!r->loops.empty() &&
+        hipMemcpyAsync(ws + L.loops, r->loops.data(), r->loops.size() * sizeof(dsr_dloop), hipMemcpyHostToDevice,
+                       s) != hipSuccess)
+        return DSR_E_HIP;
+    if (!r->init.empty() &&
+        hipMemcpyAsync(ws + L.init, r->init.data(), r->init.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        return DSR_E_HIP;
+    /* counters, error word and arrival tree start at zero; partials and
+     * stacks are written before they are read */
+    if ((rc = dsr_static_fill(ws + L.result, sizeof(dsr_dresult) / 4, 0u, stream))) return rc;
+    dsr_dlaunch LP{};
+    LP.regions = (const dsr_dregion *)(ws + L.desc);
+    LP.items = nullptr;
+    LP.n_regions = 1;
+    dsr_dconfig C = make_dconfig(c, c->cfg.wg_size, c->cfg.lds_slab_bytes, c->cfg.overflow_threshold,
+                                 c->cfg.master_joins, 0u);
+    C.hbm_base = ws + L.hbm;
+    C.nest_base = L.nested ? ws + L.nest : nullptr;
+    if (dsr_launch_region_kernel(&LP, &C, (uint32_t)r->teams, c->cfg.wg_size, c->lds_bytes, r->variant, stream) !=
+        0)
+        return DSR_E_HIP;
+    return dsr_static_copy_result(ws + L.result, r->n_red, result, stream);
 }
 
 /* ---- batched form ---------------------------------------------------------- */

@@ -165,6 +165,11 @@ struct dsr_dconfig {
 #ifdef __cplusplus
 extern "C" {
 #endif
+/* The fixed device workspace (dsr_static.hip): its address on `device`,
+ * a word fill kernel and the result-record copy kernel. */
+int dsr_static_workspace(int device, uint8_t **out);
+int dsr_static_fill(void *p, uint32_t words, uint32_t value, void *stream);
+int dsr_static_copy_result(const void *result_block, uint32_t n_red, void *dst, void *stream);
 /* Kernel launchers (dsr_dispatch.cpp). Return hipError_t as int. */
 int dsr_launch_region_kernel(const dsr_dlaunch *lp, const dsr_dconfig *cfg, uint32_t grid,
                              uint32_t wg_size, uint32_t lds_bytes, uint32_t variant,

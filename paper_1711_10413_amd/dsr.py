@@ -57,7 +57,8 @@ EXPORTS = ("dsr_init", "dsr_destroy", "dsr_region_begin", "dsr_push", "dsr_publi
            "dsr_batch_elapsed", "dsr_batch_free", "dsr_autotune", "dsr_batch_replay_serial",
            "dsr_serve_start", "dsr_serve_submit", "dsr_serve_poll", "dsr_serve_pending",
            "dsr_serve_replay", "dsr_serve_stop", "dsr_occupancy_model", "dsr_region_occupancy",
-           "dsr_publish_list", "dsr_control_bytes", "dsr_serve_status")
+           "dsr_publish_list", "dsr_control_bytes", "dsr_serve_status", "dsr_launch_static",
+           "dsr_static_bytes")
 
 
 class dsr_ref(C.Structure):
@@ -106,6 +107,20 @@ class dsr_done(C.Structure):
             fx.append(_fixed([w[0], w[1], w[2]]))
         return {"ticket": self.ticket, "status": self.status, "f64": list(self.f64[:self.n_red]),
                 "i64": list(self.i64[:self.n_red]), "fixed": fx, "device_us": self.device_us}
+
+
+class dsr_result_rec(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_red", C.c_int32), ("f64", C.c_double * 8),
+                ("i64", C.c_int64 * 8), ("fixed", (C.c_uint64 * 3) * 8)]
+
+    def as_dict(self):
+        fx = [_fixed([w[0], w[1], w[2]]) for w in list(self.fixed)[:self.n_red]]
+        return {"status": self.status, "f64": list(self.f64[:self.n_red]),
+                "i64": list(self.i64[:self.n_red]), "fixed": fx}
+
+
+DSR_STATIC_SCRATCH_BYTES = 16 << 20
+RESULT_REC_BYTES = C.sizeof(dsr_result_rec)
 
 
 class dsr_serve_stat(C.Structure):
@@ -172,6 +187,7 @@ def lib():
             "dsr_publish_list": [P, C.POINTER(dsr_ref), i32, i32, C.POINTER(dsr_loop)],
             "dsr_pop": [P, i32],
             "dsr_launch": [P, P],
+            "dsr_launch_static": [P, P, P],
             "dsr_region_sync": [P],
             "dsr_region_reduction": [P, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                      C.POINTER(C.c_uint64)],
@@ -214,6 +230,8 @@ def lib():
         L.dsr_strerror.restype = C.c_char_p
         L.dsr_control_bytes.argtypes = [u32]
         L.dsr_control_bytes.restype = u32
+        L.dsr_static_bytes.argtypes = [P]
+        L.dsr_static_bytes.restype = C.c_uint64
         _lib = L
     return _lib
 
@@ -287,6 +305,23 @@ def dsr_pop(region, frame):
 
 def dsr_launch(region, stream=0):
     return _check(lib().dsr_launch(region, stream or None), "dsr_launch")
+
+
+def dsr_launch_static(region, result_ptr, stream=0):
+    """Launch without allocating: every device buffer in the library's fixed
+    workspace; the result record (RESULT_REC_BYTES) goes to the device
+    address `result_ptr`."""
+    return _check(lib().dsr_launch_static(region, result_ptr, stream or None), "dsr_launch_static")
+
+
+def dsr_static_bytes(region):
+    return int(lib().dsr_static_bytes(region))
+
+
+def result_rec(raw):
+    """Decode a dsr_result_rec from its bytes (e.g. a copied-back tensor)."""
+    rec = dsr_result_rec.from_buffer_copy(bytes(raw))
+    return rec.as_dict()
 
 
 def dsr_region_sync(region):

@@ -19,7 +19,7 @@ def declared_symbols():
         if not h.endswith(".h") or h == "dsr_device.h":
             continue
         text = open(os.path.join(ROOT, "include", h)).read()
-        names |= set(re.findall(r"^\s*(?:int|uint32_t|const char \*)\s*(dsr_\w+)\s*\(", text, re.M))
+        names |= set(re.findall(r"^\s*(?:int|uint32_t|uint64_t|const char \*)\s*(dsr_\w+)\s*\(", text, re.M))
     return names
 
 
@@ -248,4 +248,27 @@ def test_nested_depth_is_checked_on_the_host():
             got = e.code
         assert got == code, depth
         D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+
+
+def test_static_launch_host_checks():
+    """The launch without allocation rejects, before any device work, a
+    region whose buffers exceed the fixed workspace, a live frame and a
+    missing result pointer."""
+    ctx = host_ctx(wg_size=256, lds_slab_bytes=4096, hbm_slab_bytes=65536, max_teams=1024)
+    r = D.dsr_region_begin(ctx, 256)           # 256 x 64 KiB stack slots = 16 MiB + program
+    f = D.dsr_push(r, 24, D.affine_xor_frame(1, 2, 3, 4))
+    assert D.lib().dsr_launch_static(r, 16, None) == D.DSR_E_LIVE
+    D.dsr_publish(r, f, D.DSR_BODY_AFFINE_XOR, 1024, out=16)
+    D.dsr_pop(r, f)
+    assert D.dsr_static_bytes(r) > D.DSR_STATIC_SCRATCH_BYTES
+    assert D.lib().dsr_launch_static(r, 16, None) == D.DSR_E_NOMEM
+    assert D.lib().dsr_launch_static(r, None, None) == D.DSR_E_INVAL
+    r2 = D.dsr_region_begin(ctx, 128)
+    f = D.dsr_push(r2, 24, D.affine_xor_frame(1, 2, 3, 4))
+    D.dsr_publish(r2, f, D.DSR_BODY_AFFINE_XOR, 1024, out=16)
+    D.dsr_pop(r2, f)
+    assert 128 * 65536 < D.dsr_static_bytes(r2) <= D.DSR_STATIC_SCRATCH_BYTES
+    D.dsr_region_free(r)
+    D.dsr_region_free(r2)
     D.dsr_destroy(ctx)
