@@ -281,6 +281,11 @@ int dsr_region_reduction(dsr_region *r, int32_t index, int64_t *i64, double *f64
  *                         last team, the cross-team combine) was done
  *   [89 .. 91]            last reference list published: where (3 on chip,
  *                         1 HBM list frame), its offset, its entries (0: none)
+ *   [92], [93]            low words of the wall clock when the team's
+ *                         partials were stored and when its arrival atomic
+ *                         returned
+ *   [94], [95]            the team that combined the partials (the last to
+ *                         arrive): when it began and when it finished
  *   [96 + 2w, 97 + 2w]    low words of the wall clock when wave w started
  *                         and finished its share of the last body it ran
  *   [128 + 8m .. 135 + 8m] nested member m (last nested body): its frame's
@@ -572,10 +577,23 @@ int dsr_occupancy_model(const dsr_hw_model *hw, uint32_t threads_per_team,
                         dsr_occupancy *out);
 
 /* The model for this runtime's region kernel on the context's device: the
- * kernel's registers per thread (compiled variant `variant`, 0..2, of the
- * context's workgroup size), the team's LDS (control block plus stack
- * slab) and the device's parameters. */
+ * kernel's registers per thread (compiled variant `variant` of the
+ * context's workgroup size: 0..2 for the general instances, which hold
+ * fixed fma chains up to 8+8, 16+16 and 32+32 scalars; 10 + k for the lean
+ * instance of fixed chain k of (1,0) (1,1) (2,2) (4,4) (8,8) (16,16)
+ * (32,32), which a single-region launch of workgroups up to 256 threads
+ * runs when every publish of the region is that chain), the team's LDS
+ * (control block plus stack slab) and the device's parameters. */
 int dsr_region_occupancy(dsr_ctx *ctx, uint32_t variant, dsr_occupancy *out);
+
+/* ---- measuring stick (not in the paper) -----------------------------------
+ * The streaming ceiling of the fma-chain loop: y[i] = (double)x[i] for
+ * i < n (x: n fp32, y: n fp64, device pointers), the loop's 4 B read and
+ * 8 B write per element with no runtime around it: `grid` workgroups of
+ * `wg_size` threads (a multiple of 64, at most 1024), each streaming one
+ * contiguous chunk.  Asynchronous on `stream`.  DSR_E_INVAL for a bad shape
+ * or a null buffer with n > 0. */
+int dsr_stream_ceiling(const float *x, double *y, uint64_t n, uint32_t grid, uint32_t wg_size, void *stream);
 
 /* Static string for a DSR_* code. */
 const char *dsr_strerror(int code);

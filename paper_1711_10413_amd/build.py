@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libdsr.so")
 KERNEL = os.path.join(CSRC, "dsr_kernels.hip")
 HOST_SOURCES = [os.path.join(CSRC, "dsr_api.cpp"), os.path.join(CSRC, "dsr_dispatch.cpp"),
-                os.path.join(CSRC, "dsr_static.hip")]
+                os.path.join(CSRC, "dsr_static.hip"), os.path.join(CSRC, "dsr_ceiling.hip")]
 SOURCES = [KERNEL] + HOST_SOURCES
 HEADERS = [os.path.join(CSRC, "dsr_internal.h"), os.path.join(ROOT, "include", "dsr_device.h"),
            os.path.join(ROOT, "include", "dsr.h")]

@@ -50,6 +50,8 @@ struct dsr_region {
     uint32_t n_red;
     uint32_t red_kind_mask;
     uint32_t variant;                   /* widest fixed fma chain published */
+    int32_t lean;                       /* lean instance chain every publish uses
+                                           (-1 none yet, -2 mixed or other bodies) */
     bool frozen;                        /* uploaded; program can't change   */
     /* device side */
     dsr_op *d_ops;
@@ -158,6 +160,7 @@ extern "C" int dsr_region_begin(dsr_ctx *ctx, int32_t teams, dsr_region **out)
     r->n_red = 0;
     r->red_kind_mask = 0;
     r->variant = 0;
+    r->lean = -1;
     r->frozen = false;
     r->d_ops = nullptr;
     r->d_loops = nullptr;
@@ -275,6 +278,27 @@ static bool lane_share_ok(const dsr_region *r, uint64_t chunk)
     return (chunk + lanes - 1) / lanes <= (1ull << 15);
 }
 
+/* The lean chain a publish of `body` over loop L would run on, or -2. */
+static int32_t lean_chain_of(int32_t body, const dsr_loop &L)
+{
+    if (body != DSR_BODY_FMA_CHAIN || L.alen != 0 || L.schedule != DSR_SCHED_STATIC) return -2;
+    for (int32_t k = 0; k < DSR_LEAN_CHAINS; ++k)
+        if ((int)L.ni == DSR_LEAN_NI(k) && (int)L.nf == DSR_LEAN_NF(k)) return k;
+    return -2;
+}
+
+static void note_lean(dsr_region *r, int32_t k)
+{
+    if (r->lean == -1) r->lean = k;
+    else if (r->lean != k) r->lean = -2;
+}
+
+/* Kernel variant for a single-region launch of r with workgroups of wg. */
+static uint32_t single_variant(const dsr_region *r, uint32_t wg)
+{
+    return (r->lean >= 0 && wg <= 256) ? (uint32_t)(DSR_LEAN_BASE + r->lean) : r->variant;
+}
+
 extern "C" int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr_loop *loop)
 {
     if (!r || !loop) return DSR_E_INVAL;
@@ -337,6 +361,7 @@ extern "C" int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr
     } catch (...) {
         return DSR_E_NOMEM;
     }
+    note_lean(r, lean_chain_of(body, L));
     return DSR_OK;
 }
 
@@ -386,6 +411,7 @@ extern "C" int dsr_publish_list(dsr_region *r, const dsr_ref *refs, int32_t n, i
     } catch (...) {
         return DSR_E_NOMEM;
     }
+    note_lean(r, -2);
     r->red_kind_mask |= 1u << r->n_red;
     r->n_red++;
     return DSR_OK;
@@ -507,8 +533,8 @@ extern "C" int dsr_launch(dsr_region *r, void *stream)
      * launches costs about as much as a small region's fixed overhead */
     const bool timing = (c->cfg.flags & DSR_F_TIMING) != 0;
     if (timing && hipEventRecord(r->ev0, s) != hipSuccess) return DSR_E_HIP;
-    if (dsr_launch_region_kernel(&LP, &C, (uint32_t)r->teams, c->cfg.wg_size, c->lds_bytes, r->variant,
-                                 stream) != 0)
+    if (dsr_launch_region_kernel(&LP, &C, (uint32_t)r->teams, c->cfg.wg_size, c->lds_bytes,
+                                 single_variant(r, c->cfg.wg_size), stream) != 0)
         return DSR_E_HIP;
     if (timing && hipEventRecord(r->ev1, s) != hipSuccess) return DSR_E_HIP;
     r->stream = s;
@@ -684,8 +710,8 @@ extern "C" int dsr_launch_static(dsr_region *r, dsr_result_rec *result, void *st
                                  c->cfg.master_joins, 0u);
     C.hbm_base = ws + L.hbm;
     C.nest_base = L.nested ? ws + L.nest : nullptr;
-    if (dsr_launch_region_kernel(&LP, &C, (uint32_t)r->teams, c->cfg.wg_size, c->lds_bytes, r->variant, stream) !=
-        0)
+    if (dsr_launch_region_kernel(&LP, &C, (uint32_t)r->teams, c->cfg.wg_size, c->lds_bytes,
+                                 single_variant(r, c->cfg.wg_size), stream) != 0)
         return DSR_E_HIP;
     return dsr_static_copy_result(ws + L.result, r->n_red, result, stream);
 }
@@ -1599,7 +1625,10 @@ extern "C" int dsr_occupancy_model(const dsr_hw_model *hw, uint32_t threads, uin
 
 extern "C" int dsr_region_occupancy(dsr_ctx *ctx, uint32_t variant, dsr_occupancy *out)
 {
-    if (!ctx || !out || variant > 2) return DSR_E_INVAL;
+    if (!ctx || !out) return DSR_E_INVAL;
+    if (variant > 2 && (variant < DSR_LEAN_BASE || variant >= DSR_LEAN_BASE + DSR_LEAN_CHAINS ||
+                        ctx->cfg.wg_size > 256))
+        return DSR_E_INVAL;
     if (ctx->device < 0) return DSR_E_STATE;
     hipDeviceProp_t p{};
     if (hipGetDeviceProperties(&p, ctx->device) != hipSuccess) return DSR_E_HIP;

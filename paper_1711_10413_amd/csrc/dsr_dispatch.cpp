@@ -33,9 +33,16 @@ const instance kInstances[] = {DSR_INSTANCES(DSR_ENTRY)};
 
 /* Workgroups above 512 threads run the 1024-thread instance (run-time
  * chains only), 257-512 the 512-thread one; up to 256 threads the variant
- * the regions need. */
+ * the regions need, or the lean instance a single region of one fixed
+ * chain asks for. */
 const instance *pick(uint32_t wg_size, uint32_t variant)
 {
+    if (variant >= DSR_LEAN_BASE) {
+        if (wg_size > 256 || variant >= DSR_LEAN_BASE + DSR_LEAN_CHAINS) return nullptr;
+        for (const instance &k : kInstances)
+            if (k.maxwg == 256u && k.variant == (int)variant) return &k;
+        return nullptr;
+    }
     const uint32_t maxwg = wg_size > 512 ? 1024u : (wg_size > 256 ? 512u : 256u);
     const int want = maxwg == 1024 ? -1 : (maxwg == 512 ? 0 : (int)(variant > 2 ? 2 : variant));
     for (const instance &k : kInstances)

@@ -160,7 +160,22 @@ struct dsr_dconfig {
     X(256_1, 256, 1)     \
     X(256_2, 256, 2)     \
     X(512_0, 512, 0)     \
-    X(1024_m1, 1024, -1)
+    X(1024_m1, 1024, -1) \
+    X(256_l0, 256, 10)   \
+    X(256_l1, 256, 11)   \
+    X(256_l2, 256, 12)   \
+    X(256_l3, 256, 13)   \
+    X(256_l4, 256, 14)   \
+    X(256_l5, 256, 15)   \
+    X(256_l6, 256, 16)
+
+/* Lean instances: variant DSR_LEAN_BASE + k runs single-region launches of
+ * workgroups up to 256 threads whose publishes are all the fixed fma chain
+ * k, (DSR_LEAN_NI(k) int32, DSR_LEAN_NF(k) fp64 scalars), with no array. */
+#define DSR_LEAN_BASE 10
+#define DSR_LEAN_CHAINS 7
+#define DSR_LEAN_NI(k) ((k) == 0 ? 1 : (k) == 1 ? 1 : (k) == 2 ? 2 : (k) == 3 ? 4 : (k) == 4 ? 8 : (k) == 5 ? 16 : 32)
+#define DSR_LEAN_NF(k) ((k) == 0 ? 0 : DSR_LEAN_NI(k))
 
 #ifdef __cplusplus
 extern "C" {

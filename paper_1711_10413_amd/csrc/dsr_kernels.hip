@@ -255,6 +255,13 @@ struct span_t {
  * some one.  Measured on the fma chains against the fixed per-lane share:
  * 2.2-2.7 us faster per 2^24-element region for up to 16 scalars, 0.5-1.2 us
  * for 32 and 64; 2048-, 4096- and 8192-iteration blocks were slower. */
+/* teams up to this many arrive at one counter (no group level) */
+#ifndef DSR_FLAT_TEAMS
+#define DSR_FLAT_TEAMS 512
+#endif
+#ifndef DSR_ARRIVE_FENCE
+#define DSR_ARRIVE_FENCE 1
+#endif
 #ifndef DSR_TEAM_BLOCK
 #define DSR_TEAM_BLOCK 1024u
 #endif
@@ -978,12 +985,12 @@ __device__ __forceinline__ void body_gather_nested(team_t &T, frame_t outer, con
  * before reading the partials, once per group. */
 __device__ __forceinline__ void store_dev(uint64_t *p, uint64_t v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store((GLB uint64_t *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint64_t load_dev(const uint64_t *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load((const GLB uint64_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void drain_memory() { __builtin_amdgcn_s_waitcnt(0); }
@@ -1002,12 +1009,28 @@ __device__ __forceinline__ const uint8_t *frame_ptr(const team_t &T, frame_t f)
  * 512 threads); 1: adds 16+16; 2: adds 32+32; -1 (workgroups above 512
  * threads, 128 registers per lane): run-time chains only.  Other lengths
  * (at most 64 scalars) use the run-time chain, one pair per batch at -1. */
+/* Lean instances (VARIANT >= DSR_LEAN_BASE) run single-region launches
+ * whose every publish is one fixed fma chain, DSR_LEAN_NI/NF of the
+ * variant: the kernel then holds only that body and only the single-region
+ * form, so its code and registers are those of the sweep's own path. */
+template <int VARIANT>
+struct lean_chain {
+    static constexpr int k = VARIANT - DSR_LEAN_BASE;
+    static constexpr int ni = DSR_LEAN_NI(k), nf = DSR_LEAN_NF(k);
+};
+
 template <int VARIANT>
 __device__ __forceinline__ void run_body(team_t &T, uint32_t body, frame_t f, const dsr_dloop &L, span_t sp,
                                          lane_acc &A, uint32_t *claim, uint32_t member,
                                          uint32_t members, uint32_t &inner_pushes, uint32_t *tr)
 {
     const uint32_t lane = T.lane;
+    if constexpr (VARIANT >= DSR_LEAN_BASE) {
+        /* the host dispatches only regions made of this chain here */
+        if (body == DSR_BODY_FMA_CHAIN)
+            body_fma_fixed<lean_chain<VARIANT>::ni, lean_chain<VARIANT>::nf>(T, f, L, sp, A, claim, lane);
+        return;
+    }
     switch (body) {
     case DSR_BODY_AFFINE_XOR: {
         /* frame layout: [8 B int64 sum][a][b][c][d] */
@@ -1136,7 +1159,7 @@ __device__ __forceinline__ void participate(team_t &T, const dsr_dregion &R, con
     /* served form: the request completes while the kernel keeps running,
      * so this wave's output stores must have reached L2 before the join
      * (the master then writes the L2 back before the team arrives) */
-    if (C.serve) drain_memory();
+    if (VARIANT < DSR_LEAN_BASE && C.serve) drain_memory();
     const i192 w = wave_sum192(widen(A));
     const uint32_t bad = __any(A.bad != 0);
     end_parallel(T, w.w0, w.w1, w.w2, bad);
@@ -1232,6 +1255,30 @@ __device__ __forceinline__ dsr_op op_at(const op_lanes &o, uint32_t k)
     return op;
 }
 
+/* Master wave: add the join's total into the shared sum at c (an int64
+ * for the integer body, else a 192-bit integer in 2^-75 units) and return
+ * the new value as 192 bits. */
+template <class P>
+__device__ __forceinline__ i192 update_sum(P c, i192 tot, bool integer_sum, uint32_t lane)
+{
+    i192 sv;
+    if (integer_sum) {
+        const int64_t nv = (int64_t)(c[0] + tot.w0);
+        sv = i192{(uint64_t)nv, (uint64_t)(nv >> 63), (uint64_t)(nv >> 63)};
+        wave_sync();
+        if (lane == 0) c[0] = (uint64_t)nv;
+    } else {
+        sv = add192(tot, i192{c[0], c[1], c[2]});
+        wave_sync();
+        if (lane == 0) {
+            c[0] = sv.w0;
+            c[1] = sv.w1;
+            c[2] = sv.w2;
+        }
+    }
+    return sv;
+}
+
 /* Master wave: the sequential code block of one region for one team
  * (Figure 2): pushes, publishes and pops.  Returns the team's error. */
 template <int VARIANT>
@@ -1266,7 +1313,7 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
                        op.nbytes);
         } else if (op.kind == DSR_OP_PUBLISH) {
             frame_t f, lf{SPACE_NONE, 0, 0};
-            if (op.body == DSR_BODY_FMA_CHAIN_REFS) {
+            if (VARIANT < DSR_LEAN_BASE && op.body == DSR_BODY_FMA_CHAIN_REFS) {
                 /* section 5.2: resolve each (frame, offset) reference to a
                  * stack address and write the list on chip, or to a list
                  * frame on the HBM stack when it is longer than the on-chip
@@ -1337,31 +1384,20 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
             if (T.lane == 0) h->bad = 0;
             if (op.red != 0xffffffffu) {
                 /* the shared sum: the frame's first bytes, or where reference
-                 * 0 of the list points */
-                uint8_t *fb;
-                if (op.body == DSR_BODY_FMA_CHAIN_REFS) {
+                 * 0 of the list points; read and written through a pointer
+                 * of its own memory space (a generic access would also wait
+                 * for this wave's outstanding loop stores) */
+                uint32_t s_space = f.space, s_off = f.off;
+                if (VARIANT < DSR_LEAN_BASE && op.body == DSR_BODY_FMA_CHAIN_REFS) {
                     const uint32_t *lst = f.space == SPACE_LIST ? ref_list(T) : (const uint32_t *)frame_hbm(T, f);
-                    const uint32_t s_space = uniform(lst[0]), s_off = uniform(lst[1]);
-                    fb = s_space == SPACE_LDS ? T.stack_lds + s_off : T.stack_hbm + s_off;
-                } else {
-                    fb = (uint8_t *)frame_ptr(T, f);
+                    s_space = uniform(lst[0]);
+                    s_off = uniform(lst[1]);
                 }
-                i192 sv;
-                if (op.body == DSR_BODY_AFFINE_XOR) {
-                    const int64_t cur = *(const int64_t *)fb;
-                    const int64_t nv = (int64_t)((uint64_t)cur + tot.w0);
-                    sv = i192{(uint64_t)nv, (uint64_t)(nv >> 63), (uint64_t)(nv >> 63)};
-                    wave_sync();
-                    if (T.lane == 0) *(int64_t *)fb = nv;
-                } else {
-                    const uint64_t *c = (const uint64_t *)fb;
-                    sv = add192(tot, i192{c[0], c[1], c[2]});
-                    wave_sync();
-                    if (T.lane == 0) {
-                        uint64_t *cw = (uint64_t *)fb;
-                        cw[0] = sv.w0; cw[1] = sv.w1; cw[2] = sv.w2;
-                    }
-                }
+                const bool integer_sum = op.body == DSR_BODY_AFFINE_XOR;
+                const i192 sv = s_space == SPACE_LDS
+                                    ? update_sum((LDSQ uint64_t *)(dsr_lds + cb_bytes(T.nw) + s_off), tot, integer_sum,
+                                                 T.lane)
+                                    : update_sum((GLB uint64_t *)(T.stack_hbm + s_off), tot, integer_sum, T.lane);
                 if (T.lane == 0) {
                     uint64_t *pp = R.partials + ((uint64_t)op.red * R.teams + team) * DSR_PART_WORDS;
                     store_dev(pp, sv.w0);
@@ -1416,18 +1452,39 @@ __device__ __forceinline__ i192 sum_partials(const uint64_t *base, uint32_t cnt,
     return wave_sum192(s);
 }
 
+/* The region descriptor fields the arrival and the combine use, held in
+ * registers: read once before the arrival atomics, so no fence between
+ * them makes the last team reload the descriptor from memory. */
+struct region_sums {
+    uint64_t *partials;
+    dsr_dresult *result;
+    uint32_t teams, n_red, red_kind_mask;
+};
+
+__device__ __forceinline__ region_sums sums_of(const dsr_dregion &R)
+{
+    region_sums S;
+    S.partials = R.partials;
+    S.result = R.result;
+    S.teams = uniform(R.teams);
+    S.n_red = uniform(R.n_red);
+    S.red_kind_mask = uniform(R.red_kind_mask);
+    return S;
+}
+
 /* Last team: the region's reductions from the (group) partials, exact in
  * 192-bit integers, rounded once for fp64. */
-__device__ __forceinline__ void combine_teams(const dsr_dregion &R, uint32_t cnt, uint32_t stride, uint32_t lane)
+__device__ __forceinline__ void combine_teams(const region_sums &R, uint32_t cnt, uint32_t stride, uint32_t lane)
 {
     for (uint32_t r = 0; r < R.n_red; ++r) {
         const i192 s = sum_partials(R.partials + (uint64_t)r * R.teams * DSR_PART_WORDS, cnt, stride, lane);
         if (lane == 0) {
-            R.result->fixed[r][0] = s.w0;
-            R.result->fixed[r][1] = s.w1;
-            R.result->fixed[r][2] = s.w2;
-            R.result->i64[r] = (int64_t)s.w0;
-            R.result->f64[r] = ((R.red_kind_mask >> r) & 1u) ? fixed_to_double(s) : (double)(int64_t)s.w0;
+            GLB dsr_dresult *res = (GLB dsr_dresult *)R.result;
+            res->fixed[r][0] = s.w0;
+            res->fixed[r][1] = s.w1;
+            res->fixed[r][2] = s.w2;
+            res->i64[r] = (int64_t)s.w0;
+            res->f64[r] = ((R.red_kind_mask >> r) & 1u) ? fixed_to_double(s) : (double)(int64_t)s.w0;
         }
     }
 }
@@ -1457,23 +1514,27 @@ __device__ __forceinline__ void publish_record(const dsr_dregion &R, dsr_drec *r
  * reads every partial in one round; with more, the last team of each group
  * first adds up its group's partials and leaves the sum in the group's
  * first partial slot, and the last team overall adds the group sums. */
-__device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team, uint32_t lane,
-                                            uint64_t *done_ts, dsr_drec *rec = nullptr)
+__device__ __forceinline__ void finish_team(const dsr_dregion &RD, uint32_t team, uint32_t lane,
+                                            uint64_t *done_ts, dsr_drec *rec = nullptr, uint32_t *tr = nullptr)
 {
-    const uint32_t gsize = (R.teams + DSR_ARRIVE_GROUPS - 1) / DSR_ARRIVE_GROUPS;
+    const region_sums R = sums_of(RD);
+    const uint32_t gsize = R.teams <= DSR_FLAT_TEAMS ? R.teams : (R.teams + DSR_ARRIVE_GROUPS - 1) / DSR_ARRIVE_GROUPS;
     const uint32_t ngroups = (R.teams + gsize - 1) / gsize;
     const uint32_t g = team / gsize;
     const uint32_t in_group = min(gsize, R.teams - g * gsize);
     const bool group_sums = R.teams > 512;
     drain_memory();                      /* this team's partials are stored */
+    if (tr && lane == 0) tr[92] = (uint32_t)wall_clock64();
+    GLB dsr_dresult *res = (GLB dsr_dresult *)R.result;
     uint32_t prev = 0;
     if (lane == 0)
-        prev = __hip_atomic_fetch_add(&R.result->group[g * 16], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        prev = __hip_atomic_fetch_add(&res->group[g * 16], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     prev = uniform((uint32_t)__shfl((int)prev, 0, 64));
+    if (tr && lane == 0) tr[93] = (uint32_t)wall_clock64();
     if (prev != in_group - 1) return;
     /* the last arriver of a group reads the others' partials: acquire */
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (lane == 0) __hip_atomic_store(&R.result->group[g * 16], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (DSR_ARRIVE_FENCE) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (lane == 0) __hip_atomic_store(&res->group[g * 16], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (ngroups > 1) {
         if (group_sums) {
             for (uint32_t r = 0; r < R.n_red; ++r) {
@@ -1488,24 +1549,27 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &R, uint32_t team,
             drain_memory();              /* the group sums are stored */
         }
         if (lane == 0)
-            prev = __hip_atomic_fetch_add(&R.result->arrived, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            prev = __hip_atomic_fetch_add(&res->arrived, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         prev = uniform((uint32_t)__shfl((int)prev, 0, 64));
         if (prev != ngroups - 1) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (lane == 0) __hip_atomic_store(&R.result->arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (DSR_ARRIVE_FENCE) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (lane == 0) __hip_atomic_store(&res->arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    if (tr && lane == 0) tr[94] = (uint32_t)wall_clock64();
+    /* the error word, the partials and the counters are read and reset in
+     * one round trip: nothing below waits on anything but the loads */
     int32_t err = 0;
-    if (lane == 0) err = __hip_atomic_exchange(&R.result->error, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) err = __hip_atomic_exchange(&res->error, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane < DSR_MAX_LOOPS) __hip_atomic_store(&res->claim[lane], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (ngroups > 1 && group_sums) combine_teams(R, ngroups, gsize, lane);
     else combine_teams(R, R.teams, 1, lane);
-    if (lane < DSR_MAX_LOOPS)
-        __hip_atomic_store(&R.result->claim[lane], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (lane == 0) {
-        R.result->final_error = err;
-        R.result->done += 1;
+        res->final_error = err;
+        __hip_atomic_fetch_add(&res->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (done_ts) *done_ts = wall_clock64();
+        if (tr) tr[95] = (uint32_t)wall_clock64();
     }
-    if (rec) publish_record(R, rec, lane);
+    if (rec) publish_record(RD, rec, lane);
 }
 
 /* Served form: close the server (one workgroup does it; see wait_item).
@@ -1672,9 +1736,10 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
                          C.hbm_base + (uint64_t)blockIdx.x * C.hbm_slot_bytes, (uint32_t)C.hbm_slot_bytes);
     T.nest_hbm = C.nest_base + (uint64_t)blockIdx.x * DSR_NEST_SLOT;
     T.nest_global = C.nest_global;
-    const bool single = LP.items == nullptr;
+    constexpr bool lean = VARIANT >= DSR_LEAN_BASE;
+    const bool single = lean || LP.items == nullptr;
     uint32_t barriers = 0, inner_pushes = 0;
-    if (LP.published && T.wave == C.nw - 1 && T.lane == 0) {
+    if (!lean && LP.published && T.wave == C.nw - 1 && T.lane == 0) {
         const uint64_t now = wall_clock64();
         if (blockIdx.x == 0 && LP.done_ts)
             __hip_atomic_store(LP.done_ts, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1713,18 +1778,17 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
                 }
                 team_reset(T);
             }
-            const dsr_dregion &R = C.serve ? stage_request(T, LP.regions + region) : LP.regions[region];
+            const dsr_dregion &R = (!lean && C.serve) ? stage_request(T, LP.regions + region) : LP.regions[region];
             run_program<VARIANT>(T, R, C, region, team, barriers, inner_pushes);
             uint32_t *tr = (single && C.trace && R.trace) ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
             if (tr && T.lane == 0) tr[87] = (uint32_t)wall_clock64();
-            if (C.serve) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); /* outputs out of L2 */
+            if (!lean && C.serve) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); /* outputs out of L2 */
             /* the 1024-thread instance reads fewer partials per round */
-            finish_team(R, team, T.lane,
-                                             (LP.done_ts && !LP.published) ? LP.done_ts + region : nullptr,
-                                             LP.recs ? LP.recs + region : nullptr);
+            finish_team(R, team, T.lane, (LP.done_ts && !LP.published) ? LP.done_ts + region : nullptr,
+                        (!lean && LP.recs) ? LP.recs + region : nullptr, tr);
             if (tr && T.lane == 0) tr[88] = (uint32_t)wall_clock64();
         }
-        if (LP.wg_exited && T.lane == 0)
+        if (!lean && LP.wg_exited && T.lane == 0)
             __hip_atomic_store(LP.wg_exited + blockIdx.x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         /* terminate the workers (Figure 3's terminate branch) */
         frame_t none{SPACE_NONE, 0, 0};
@@ -1745,7 +1809,7 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
             barriers++;
             if (!go) break;
             const uint32_t region = uniform(header(T)->region), team = uniform(header(T)->team);
-            participate<VARIANT>(T, C.serve ? *serve_area(T) : LP.regions[region], C, team, body, f, loop,
+            participate<VARIANT>(T, (!lean && C.serve) ? *serve_area(T) : LP.regions[region], C, team, body, f, loop,
                                  inner_pushes);
             barriers++;
         }

@@ -58,7 +58,7 @@ EXPORTS = ("dsr_init", "dsr_destroy", "dsr_region_begin", "dsr_push", "dsr_publi
            "dsr_serve_start", "dsr_serve_submit", "dsr_serve_poll", "dsr_serve_pending",
            "dsr_serve_replay", "dsr_serve_stop", "dsr_occupancy_model", "dsr_region_occupancy",
            "dsr_publish_list", "dsr_control_bytes", "dsr_serve_status", "dsr_launch_static",
-           "dsr_static_bytes")
+           "dsr_static_bytes", "dsr_stream_ceiling")
 
 
 class dsr_ref(C.Structure):
@@ -188,6 +188,7 @@ def lib():
             "dsr_pop": [P, i32],
             "dsr_launch": [P, P],
             "dsr_launch_static": [P, P, P],
+            "dsr_stream_ceiling": [P, P, C.c_uint64, u32, u32, P],
             "dsr_region_sync": [P],
             "dsr_region_reduction": [P, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                      C.POINTER(C.c_uint64)],
@@ -314,6 +315,12 @@ def dsr_launch_static(region, result_ptr, stream=0):
     return _check(lib().dsr_launch_static(region, result_ptr, stream or None), "dsr_launch_static")
 
 
+def dsr_stream_ceiling(x_ptr, y_ptr, n, grid, wg_size=256, stream=0):
+    """The streaming ceiling kernel: y = double(x) over n elements."""
+    return _check(lib().dsr_stream_ceiling(x_ptr or None, y_ptr or None, n, grid, wg_size, stream or None),
+                  "dsr_stream_ceiling")
+
+
 def dsr_static_bytes(region):
     return int(lib().dsr_static_bytes(region))
 
@@ -356,6 +363,8 @@ def dsr_region_trace(region, team):
             "error": C.c_int32(t[81]).value,
             "t_start": t[82] | (t[83] << 32), "t_end": t[84] | (t[85] << 32),
             "t_team": t[86], "t_program_end": t[87], "t_arrived": t[88],
+            "t_partials_stored": t[92], "t_arrival_returned": t[93],
+            "t_combine_start": t[94], "t_combine_end": t[95],
             "list": (("lds", "hbm", "none", "onchip")[t[89]], t[90], t[91]) if t[91] else None,
             "wave_loop": [(t[96 + 2 * w], t[97 + 2 * w]) for w in range(16)],
             "nested": [{"frame": _nest_place(t[128 + 8 * m]),

@@ -14,7 +14,7 @@ from paper_1711_10413_amd import build as B
 def test_no_scratch_and_register_budget():
     res = B.kernel_resources()
     names = [n for n in res if "dsr_region_kernel" in n]
-    assert len(names) == 5, res
+    assert len(names) == len(B.instances()), res
     for n in names:
         r = res[n]
         assert r["scratch"] == 0, (n, r)
