@@ -90,11 +90,16 @@ def time_sweep(torch, D, regions, ks, steps, warmup, stream):
     return secs, per_k
 
 
+LEAN_CHAINS = [(1, 0), (1, 1), (2, 2), (4, 4), (8, 8), (16, 16), (32, 32)]
+STREAM_KS = (1, 2, 4, 8, 16)       # the HBM-bound chains timed as the dominant kernel
+DOMINANT = "dsr_region_kernel<256, 10..14>"
+
+
 def kernel_variant(K):
-    """Compiled variant of the region kernel a K-scalar sweep region runs
-    (fixed chains up to 8+8 in variant 0, 16+16 in 1, 32+32 in 2)."""
-    ni, nf = (K + 1) // 2, K // 2
-    return 0 if max(ni, nf) <= 8 else (1 if max(ni, nf) <= 16 else 2)
+    """Compiled instance of the region kernel a K-scalar sweep region runs:
+    the lean instance 10 + k of fixed chain k ((1,0) (1,1) (2,2) (4,4)
+    (8,8) (16,16) (32,32) int32/fp64 scalars), which holds only that chain."""
+    return 10 + LEAN_CHAINS.index(((K + 1) // 2, K // 2))
 
 
 def run_sweep(torch, np, D, W, args, stream):
@@ -255,12 +260,13 @@ def traffic_from_counters(fetch_csv, write_csv, fetch_cmd, write_cmd):
     cal = cal[0]
     f_scale = 4 * CALIB_N / (1024 * statistics.mean(fetch[cal]))
     w_scale = 8 * CALIB_N / (1024 * statistics.mean(write[cal]))
-    name = "dsr_region_kernel<256, 0>"
-    keys = [k for k in fetch if k.startswith("void dsr_region_kernel<256, 0>")]
-    if len(keys) != 1:
-        raise SystemExit("region kernel not found: %s" % keys)
-    fk = statistics.mean(fetch[keys[0]]) * 1024 * f_scale
-    wk = statistics.mean(write[keys[0]]) * 1024 * w_scale
+    name = DOMINANT
+    keys = [k for k in fetch if any(k.startswith("void dsr_region_kernel<256, %d>" % kernel_variant(K))
+                                    for K in STREAM_KS)]
+    if len(keys) != len(STREAM_KS):
+        raise SystemExit("region kernel instances not found: %s" % keys)
+    fk = statistics.mean(v for k in keys for v in fetch[k]) * 1024 * f_scale
+    wk = statistics.mean(v for k in keys for v in write[k]) * 1024 * w_scale
     lines = [
         "# HBM traffic of %s on the scalar sweep (K <= 16 regions)" % name, "",
         "Per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) from two rocprofv3 counter runs,",
@@ -289,10 +295,13 @@ def traffic_from_counters(fetch_csv, write_csv, fetch_cmd, write_cmd):
 
 # ---- publish by reference list (section 5.2) ---------------------------------------
 def run_lists(torch, np, D, W, stream, reps=20):
-    """The sweep's fma chain published three ways, per launch: one frame
-    (this runtime's form), a list of references on chip (up to 20), and the
-    same list in global memory (DSR_F_GLOBAL_LISTS), at the sweep's size
-    and at a small size where per-region costs dominate."""
+    """The sweep's fma chain published five ways, per launch: one frame
+    (this runtime's form), a list of references on chip (up to 20), the
+    same list in global memory (DSR_F_GLOBAL_LISTS), and both lists read
+    again on every batch of the loop (deref=1: each chain step reads the
+    reference, then the scalar, as outlined code must when the loop's stores
+    may alias the shared variables); at the sweep's size and at a small size
+    where per-region costs dominate."""
     from oracle import ref as R
     dev = torch.device("cuda:0")
     out = {}
@@ -308,7 +317,8 @@ def run_lists(torch, np, D, W, stream, reps=20):
             refs = [(0, 0)] + [(0, 24 + 8 * nf + 4 * k) for k in range(ni)] + [(0, 24 + 8 * k) for k in range(nf)]
             want = R.exact_sum(R.fma_chain(x_np, cf.s_i32, cf.s_f64))
             row = {"references": len(refs)}
-            for mode, flags in (("frame", 0), ("list", 0), ("global_list", D.DSR_F_GLOBAL_LISTS)):
+            for mode, flags in (("frame", 0), ("list", 0), ("global_list", D.DSR_F_GLOBAL_LISTS),
+                                ("list_deref", 0), ("global_list_deref", D.DSR_F_GLOBAL_LISTS)):
                 ctx = D.dsr_init(wg_size=WG, lds_slab_bytes=4096, hbm_slab_bytes=4096, max_teams=teams,
                                  flags=flags | D.DSR_F_TRACE)
                 r = D.dsr_region_begin(ctx, teams)
@@ -317,7 +327,7 @@ def run_lists(torch, np, D, W, stream, reps=20):
                     D.dsr_publish(r, f, D.DSR_BODY_FMA_CHAIN, n, inp=x.data_ptr(), out=y.data_ptr(), ni=ni, nf=nf)
                 else:
                     D.dsr_publish_list(r, refs, D.DSR_BODY_FMA_CHAIN_REFS, n, inp=x.data_ptr(),
-                                       out=y.data_ptr(), ni=ni, nf=nf)
+                                       out=y.data_ptr(), ni=ni, nf=nf, deref=int(mode.endswith("deref")))
                 D.dsr_pop(r, f)
                 for _ in range(3):
                     D.dsr_launch(r, stream)
@@ -336,9 +346,39 @@ def run_lists(torch, np, D, W, stream, reps=20):
                 D.dsr_region_free(r)
                 D.dsr_destroy(ctx)
             rows["K%d" % K] = row
-            say("lists", n, K, {m: round(row[m]["us_per_launch"], 2) for m in ("frame", "list", "global_list")})
+            say("lists", n, K, {m: round(row[m]["us_per_launch"], 2)
+                                for m in ("frame", "list", "global_list", "list_deref", "global_list_deref")})
         out["n%d_teams%d" % (n, teams)] = rows
         del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---- streaming ceiling ------------------------------------------------------------
+def run_ceiling(torch, D, stream, reps=40):
+    """The loop's streaming ceiling (dsr_stream_ceiling: y = double(x) over
+    2^24 elements, 12 B per element, no runtime around it) at the sweep's
+    own shape (512 x 256) and at a grid that fills every CU (4096 x 256),
+    with four buffer sets rotating as in the sweep."""
+    xs = [torch.zeros(N, dtype=torch.float32, device="cuda") for _ in range(SETS)]
+    ys = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in range(SETS)]
+    out = {}
+    for grid, wg in ((TEAMS, WG), (4096, WG)):
+        for i in range(4):
+            D.dsr_stream_ceiling(xs[i % SETS].data_ptr(), ys[i % SETS].data_ptr(), N, grid, wg, stream)
+        torch.cuda.synchronize()
+        cur = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(cur)
+        for i in range(reps):
+            D.dsr_stream_ceiling(xs[i % SETS].data_ptr(), ys[i % SETS].data_ptr(), N, grid, wg, stream)
+        e1.record(cur)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        out["grid_%dx%d" % (grid, wg)] = {"us_per_launch": us, "gbs": BYTES_PER_ELEM * N / (us * 1e-6) / 1e9}
+    ok = bool(torch.equal(ys[(reps - 1) % SETS], xs[(reps - 1) % SETS].double()))
+    out["verified"] = ok
+    del xs, ys
     torch.cuda.empty_cache()
     return out
 
@@ -378,14 +418,14 @@ def run_plain(torch, np, D, W, stream):
 
 
 # ---- arrays + nesting -------------------------------------------------------
-def run_arrays(torch, np, D, W, stream, reps=6):
+def run_arrays(torch, np, D, W, stream, reps=6, shapes=None):
     from oracle import ref as R
     n, teams = 1 << 26, 2048
     lds_max = 163840 - D.dsr_control_bytes(WG)
     outs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(2)]
     res = {}
-    for A in W.CFG3_AS:
-        for length in W.CFG3_LENS:
+    for A, length in (shapes or [(a, l) for a in W.CFG3_AS for l in W.CFG3_LENS]):
+        if True:
             arrs = W.cfg3_arrays(A, length)
             frame = 4 * A * length
             row = {"frame_bytes": frame}
@@ -495,13 +535,9 @@ def run_batched(torch, np, D, W, stream, n_inst=10000, seed=3, sample=64):
     torch.cuda.synchronize()
     total_elems = int(Ls.sum())
     algo = 12.0 * total_elems
-    cands = []
-    for wg in (128, 256, 512, 1024):
-        for joins in ((0, 1) if wg <= 512 else (0,)):
-            for lds in (16384, 40960, 65536):
-                for thr in (0, 8192):
-                    cands.append(dict(wg_size=wg, lds_slab_bytes=lds, overflow_threshold=thr,
-                                      master_joins=joins, use_graph=1))
+    # candidates from the footprint/occupancy model: LDS slabs sized to the
+    # batch's stacks, pruned per predicted residency
+    cands = D.dsr_autotune_plan(b)
     best, ms = D.dsr_autotune(b, cands, reps=2, stream=stream)
     say("autotune best", best)
 
@@ -543,6 +579,8 @@ def run_batched(torch, np, D, W, stream, n_inst=10000, seed=3, sample=64):
     torch.cuda.empty_cache()
     return {"instances": n_inst, "elements": total_elems, "algorithmic_bytes": algo,
             "tuned": best, "autotune_candidates": len(cands),
+            "autotune_ms": {"%d/%d/%d" % (c["wg_size"], c["lds_slab_bytes"], c["master_joins"]): m
+                            for c, m in zip(cands, ms)},
             "persistent_graph": pers, "persistent_no_graph": plain,
             "one_launch_per_region": each,
             "speedup_vs_one_launch": each["ms"] / pers["ms"],
@@ -550,7 +588,14 @@ def run_batched(torch, np, D, W, stream, n_inst=10000, seed=3, sample=64):
 
 
 # ---- served ----------------------------------------------------------------------
-def run_served(torch, np, D, W, stream, rates, seconds, pool=1000, seed=4, slots=256):
+def run_served(torch, np, D, W, stream, rates, seconds, pool=1000, seed=4, slots=256, check=192):
+    """Poisson arrivals at each rate for `seconds`.  Request q runs instance
+    prog[q] drawn uniformly (seeded) from a pool of `pool` instances of the
+    seed-4 table (sizes log-uniform as in the batched workload), writing its
+    y into a recycled slot buffer.  Every request's exact sum is checked
+    against the oracle's.  Then `check` requests drawn from the pool are
+    submitted back to back, each with its own output buffer, so that they
+    overlap on the device, and every element of their y is checked."""
     from oracle import ref as R
     dev = torch.device("cuda:0")
     Ls, Fs, offs = instance_pool(W, pool, seed)
@@ -562,17 +607,20 @@ def run_served(torch, np, D, W, stream, rates, seconds, pool=1000, seed=4, slots
     regs, insts = build_programs(D, W, ctx, Ls, Fs, offs, seed, x.data_ptr(), y.data_ptr(), chunk)
     slot_y = [torch.empty(1 << 20, dtype=torch.float64, device=dev) for _ in range(slots)]
     torch.cuda.synchronize()
-    want = {}
-    for q in range(0, pool, 10):           # oracle results for a tenth of the pool
+    def oracle_y(q):
         ins = insts[q]
         lo = int(offs[q])
-        want[q] = R.exact_sum(R.fma_chain(x[lo:lo + ins.L].cpu().numpy(), ins.s_i32, ins.s_f64, ins.arr))
+        return R.fma_chain(x[lo:lo + ins.L].cpu().numpy(), ins.s_i32, ins.s_f64, ins.arr)
+
+    want = [R.exact_sum(oracle_y(q)) for q in range(pool)]
     b = D.dsr_batch_create(ctx, regs)
     res = {"pool_instances": pool, "seconds_per_rate": seconds, "slots": slots,
-           "request_to_instance": "request q runs instance q mod pool of the seed-4 table"}
+           "request_to_instance": "request q runs instance prog[q], drawn uniformly from the pool "
+                                  "(seeded per rate)"}
+    rng = np.random.default_rng(seed)
     for rate in rates:
         arr = W.poisson_schedule(rate, seconds, seed=seed)
-        prog = (np.arange(len(arr)) % pool).astype(np.int32)
+        prog = rng.integers(0, pool, len(arr)).astype(np.int32)
         srv = D.dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=32768, slots=slots, slot_bytes=40960,
                                 max_teams=64, idle_ms=30000)
         try:
@@ -580,24 +628,52 @@ def run_served(torch, np, D, W, stream, rates, seconds, pool=1000, seed=4, slots
                                            timeout_s=60.0)
         finally:
             D.dsr_serve_stop(srv)
-        ok = all(d["status"] == 0 for d in done)
-        ok &= all(done[q]["f64"] == [want[int(prog[q])]] for q in range(len(done))
-                  if int(prog[q]) in want)
+        bad = sum(1 for q, d in enumerate(done) if d["status"] != 0 or d["f64"] != [want[int(prog[q])]])
         span = max(float(arr[-1]), 1e-9) if len(arr) else 1e-9
         fin = float((arr + lat * 1e-6).max()) if len(arr) else 0.0
         served = {"requests": int(len(arr)), "p50_us": pct(lat, 50), "p99_us": pct(lat, 99),
-                  "instances_per_s": len(arr) / max(fin, span), "verified": bool(ok)}
+                  "instances_per_s": len(arr) / max(fin, span), "sums_checked": int(len(arr)),
+                  "sums_wrong": int(bad)}
         lat2 = D.dsr_batch_replay_serial(b, prog, arr)
         fin2 = float((arr + lat2 * 1e-6).max()) if len(arr) else 0.0
         serial = {"p50_us": pct(lat2, 50), "p99_us": pct(lat2, 99),
                   "instances_per_s": len(arr) / max(fin2, span)}
         res["%dk_per_s" % (rate // 1000)] = {"served": served, "serial_launch_sync": serial}
         say("served", rate, served, serial)
+    # outputs in the mix: requests submitted back to back, each with its own y
+    picks = rng.integers(0, pool, check)
+    outs = [torch.full((insts[int(q)].L,), -1.0, dtype=torch.float64, device=dev) for q in picks]
+    srv = D.dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=32768, slots=slots, slot_bytes=40960,
+                            max_teams=64, idle_ms=30000)
+    got, tickets = [], {}
+    try:
+        for k, q in enumerate(picks):
+            while True:
+                try:
+                    tickets[D.dsr_serve_submit(srv, regs[int(q)], [outs[k].data_ptr()])] = k
+                    break
+                except D.DsrError as e:
+                    if e.code != D.DSR_E_BUSY:
+                        raise
+                    got += D.dsr_serve_poll(srv)
+        t0 = time.time()
+        while len(got) < check and time.time() - t0 < 30:
+            got += D.dsr_serve_poll(srv)
+    finally:
+        D.dsr_serve_stop(srv)
+    ok = len(got) == check
+    for d in got:
+        k = tickets[d["ticket"]]
+        q = int(picks[k])
+        ok &= d["status"] == 0 and d["f64"] == [want[q]]
+        ok &= bool(np.array_equal(outs[k].cpu().numpy().view(np.uint64), oracle_y(q).view(np.uint64)))
+    res["outputs_in_mix"] = {"requests": int(check), "y_elements_checked": int(sum(insts[int(q)].L for q in picks)),
+                             "ok": bool(ok)}
     D.dsr_batch_free(b)
     for r in regs:
         D.dsr_region_free(r)
     D.dsr_destroy(ctx)
-    del x, y, slot_y
+    del x, y, slot_y, outs
     torch.cuda.empty_cache()
     return res
 
@@ -668,17 +744,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--parts", default="sweep,plain,arrays,lists,batched,served,cpu",
-                    help="comma list of: sweep plain arrays lists batched served cpu calib")
+    ap.add_argument("--parts", default="sweep,ceiling,plain,arrays,lists,batched,served,cpu",
+                    help="comma list of: sweep ceiling plain arrays lists batched served cpu calib")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-hbm-only", action="store_true")
     ap.add_argument("--no-phases", action="store_true",
                     help="skip the traced launches that measure the loop phase")
-    ap.add_argument("--master-joins", type=int, default=0)
+    ap.add_argument("--master-joins", type=int, default=1,
+                    help="1: the master wave runs loop iterations too (four streaming waves per team)")
     ap.add_argument("--schedule", choices=["static", "dynamic"], default="static")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of each served arrival schedule (the full workload is 60)")
     ap.add_argument("--serve-rates", default="1000,10000,50000")
+    ap.add_argument("--arrays-shapes", default="",
+                    help="comma list of AxLEN array shapes for the arrays part (default: all 16)")
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_CMD", "WRITE_CMD"),
                     help="write the HBM traffic summary from two counter runs and exit")
     args = ap.parse_args()
@@ -697,6 +776,10 @@ def main():
     from paper_1711_10413_amd import dsr as D
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    # a stream of its own: launches on the null stream pay for its implicit
+    # synchronisation with other streams (about 6 us per region launch)
+    work_stream = torch.cuda.Stream()
+    torch.cuda.set_stream(work_stream)
     stream = torch.cuda.current_stream().cuda_stream
     out = {"metric": "region instances/sec (scalar-sharing sweep, LDS team stack)",
            "value": None, "unit": "region instances/s", "n_gpus": 1, "steps": args.steps,
@@ -713,24 +796,35 @@ def main():
         sw = run_sweep(torch, np, D, W, args, stream)
         out["value"] = sw["value"]
         out["ms_per_step"] = sw["secs"] * 1e3 / args.steps
-        # the dominant kernel: the compiled variant with the most time in a step
-        ks = list(W.CFG2_KS)
-        share = {}
-        for K in ks:
-            share.setdefault(kernel_variant(K), []).append(K)
-        dom = max(share, key=lambda v: sum(sw["per_k_kernel_ms"][K] for K in share[v]))
-        avg_ms = sum(sw["per_k_kernel_ms"][K] for K in share[dom]) / len(share[dom])
+        # the dominant kernel: the region kernel's lean instances of the
+        # HBM-bound chains (K <= 16: five of the step's seven regions, one
+        # template specialised per chain length)
+        avg_ms = sum(sw["per_k_kernel_ms"][K] for K in STREAM_KS) / len(STREAM_KS)
         achieved = sw["algo_bytes"] / (avg_ms * 1e-3) / 1e9
-        name = "dsr_region_kernel<256, %d>" % dom
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": measured_traffic(name),
-                           "kernel": name, "regions": "K in %s" % share[dom],
+                           "traffic": measured_traffic(DOMINANT),
+                           "kernel": DOMINANT, "regions": "K in %s" % list(STREAM_KS),
                            "algorithmic_bytes_per_launch": sw["algo_bytes"],
                            "avg_launch_ms": avg_ms}
+        # the 64-scalar chain is bound by fp64 FMA: 2 * 64 flop per element
+        ms64 = sw["per_k_kernel_ms"].get(64)
+        if ms64:
+            tf = 2.0 * 64 * N / (ms64 * 1e-3) / 1e12
+            out["roofline_k64"] = {"bound": "fp64 valu", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s",
+                                   "frac": tf / 78.6, "kernel": "dsr_region_kernel<256, %d>" % kernel_variant(64),
+                                   "avg_launch_ms": ms64}
         for k in ("per_k_kernel_ms", "per_k_gbs", "loop_phase_us", "loop_phase_gbs",
                   "team_phases_us", "occupancy", "lds_bytes_per_team", "hbm_only_stack", "verified"):
             out[k] = sw[k]
+    if "ceiling" in parts:
+        say("ceiling")
+        ce = run_ceiling(torch, D, stream)
+        out["streaming_ceiling"] = ce
+        if "roofline" in out:
+            a = out["roofline"]["achieved"]
+            out["roofline"]["frac_of_ceiling_same_shape"] = a / ce["grid_%dx%d" % (TEAMS, WG)]["gbs"]
+            out["roofline"]["frac_of_ceiling_full_grid"] = a / ce["grid_4096x%d" % WG]["gbs"]
     if "lists" in parts:
         say("lists")
         out["reference_lists"] = run_lists(torch, np, D, W, stream)
@@ -742,7 +836,9 @@ def main():
         out["plain_region"] = run_plain(torch, np, D, W, stream)
     if "arrays" in parts:
         say("arrays")
-        out["arrays_nested"] = run_arrays(torch, np, D, W, stream)
+        shapes = [tuple(int(v) for v in t.split("x")) for t in args.arrays_shapes.split(",")] \
+            if args.arrays_shapes else None
+        out["arrays_nested"] = run_arrays(torch, np, D, W, stream, shapes=shapes)
     if "batched" in parts:
         say("batched")
         out["batched"] = run_batched(torch, np, D, W, stream)

@@ -151,7 +151,11 @@ typedef struct dsr_loop {
     uint32_t block;    /* DYNAMIC_TAIL: iterations per claim (multiple of 128,
                           at most 65536; 0 = 1024)                               */
     uint32_t depth;    /* GATHER_NESTED: parallel levels, 2 or 3 (0 = 2)        */
-    uint32_t pad;
+    uint32_t deref;    /* FMA_CHAIN_REFS: 1 = every batch of the loop reads each
+                          shared scalar through its reference again, as outlined
+                          code does when stores in the loop may alias the shared
+                          variables (section 5.1); 0 = once per body call.
+                          Scalars only (alen must be 0); 0 for other bodies    */
 } dsr_loop;
 
 /* Loop schedules.
@@ -410,6 +414,19 @@ int dsr_batch_free(dsr_batch *b);
 int dsr_autotune(dsr_batch *b, const dsr_tune *cand, int32_t n_cand, int32_t reps, void *stream,
                  dsr_tune *best, float *ms);
 
+/* Candidates for dsr_autotune from the footprint and occupancy model (the
+ * arithmetic of section 6.2 and Tables 4-7, applied to this kernel's
+ * registers and the batch's stacks on this device; not in the paper): for
+ * every workgroup size, LDS slabs sized to the batch's region stacks (the
+ * median, 90th and 99th percentile and largest peak, rounded up to 1 KiB),
+ * pruned to the largest slab per predicted number of resident teams per CU
+ * (a larger slab keeps more frames on chip at no cost in residency), with
+ * and without the master joining; ordered by predicted working waves per
+ * CU.  Writes up to `max` tunes to `out` and the number of candidates to
+ * *n_out.  DSR_E_INVAL for null arguments, DSR_E_HIP if the device cannot
+ * be queried. */
+int dsr_autotune_plan(dsr_batch *b, dsr_tune *out, int32_t max, int32_t *n_out);
+
 /* ---- served form ----------------------------------------------------------
  * Not in the paper: the served workload (Poisson-arriving region requests
  * with admission by LDS and HBM budget) built on the paper's runtime.
@@ -440,7 +457,9 @@ int dsr_autotune(dsr_batch *b, const dsr_tune *cand, int32_t n_cand, int32_t rep
 typedef struct dsr_server dsr_server;
 
 typedef struct dsr_serve_cfg {
-    dsr_tune tune;            /* resident workgroups (grid 0 = as many as fit)   */
+    dsr_tune tune;            /* resident workgroups (grid 0 = as many as fit on
+                                 the device less one per CU, or less one CU in
+                                 32 when only one fits per CU)                    */
     uint32_t slots;           /* requests in flight at most                      */
     uint32_t slot_bytes;      /* frame-image bytes per slot                      */
     uint32_t max_teams;       /* teams per request at most                       */
@@ -448,7 +467,19 @@ typedef struct dsr_serve_cfg {
     uint32_t idle_ms;         /* server exits after this long without new work  */
     uint32_t budget_pct;      /* admission budget, percent of the resident stacks
                                  (0 = 100)                                        */
+    /* LDS classes (section 7's shared memory sized to what is needed, per
+     * request): with n_classes > 0 the server runs one resident grid per
+     * class, class k's teams having class_slab[k] bytes of on-chip stack
+     * (a multiple of 16) and class_grid[k] workgroups (0: as for tune.grid
+     * with that slab, divided by the number of classes); tune's
+     * lds_slab_bytes and grid are then unused.  A request is admitted to
+     * the smallest class whose slab holds its whole stack (dsr_serve_class_for),
+     * or, while that class is full or closed, to the next larger one. */
+    uint32_t n_classes;       /* 0: one class, tune.lds_slab_bytes            */
+    uint32_t class_slab[4];
+    uint32_t class_grid[4];
 } dsr_serve_cfg;
+#define DSR_SERVE_CLASSES 4
 
 typedef struct dsr_done {
     uint64_t ticket;
@@ -459,12 +490,23 @@ typedef struct dsr_done {
     uint64_t fixed[8][3];
     double device_us;         /* device completion time, microseconds on the
                                  device clock since the server started           */
+    int32_t lds_class;        /* the LDS class that ran the request              */
+    int32_t pad;
 } dsr_done;
 
 /* Launch the server kernel on its own stream (not in the paper).  Regions submitted later must
  * belong to `ctx` and use one of the bodies compiled into the server (all
  * bodies; fixed-length fma chains up to 8+8 scalars, longer ones through the
- * run-time loop). */
+ * run-time loop).  The server's kernel stays resident until it closes, and
+ * other device work shares the CUs with it: the runtime's copies
+ * (host<->device, staged or not) and fills run as kernels, so a grid that
+ * holds every workgroup slot of the device (an explicit grid at the
+ * occupancy limit) makes them wait until the server closes, and a caller
+ * blocked on one then sees the server close after idle_ms with its later
+ * submits failing with DSR_E_STATE.  The default grid leaves room for them.
+ * A device-wide synchronisation, or an allocation or free that performs
+ * one, also waits for the resident kernel: allocate the buffers requests use
+ * before starting the server. */
 int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_server **out);
 
 /* Submit region `program` (not launched itself; its frames all popped) (not
@@ -527,9 +569,21 @@ typedef struct dsr_serve_stat {
     uint32_t final_items;
     uint32_t published;
     uint32_t in_flight;
-    uint32_t pad;
+    uint32_t classes;         /* LDS classes (resident grids)                    */
+    /* the first class to close: why (0 open, 1 stop, 2 idle), its closing
+     * workgroup, the item that workgroup waited for, the published count
+     * it saw and the idle time it measured (microseconds) */
+    uint32_t close_reason, close_block, close_item, close_seen;
+    double close_idle_us;
 } dsr_serve_stat;
 int dsr_serve_status(dsr_server *s, dsr_serve_stat *out);
+
+/* The LDS class a request with program `r` is admitted to among `n`
+ * classes of on-chip stack sizes `slabs` (1 <= n <= DSR_SERVE_CLASSES): the
+ * smallest slab that holds the request's whole stack (the largest sum of
+ * its live frames, each rounded up to 16 bytes), else the largest slab.
+ * Host-only; returns the class index or DSR_E_INVAL. */
+int dsr_serve_class_for(const uint32_t *slabs, int32_t n, const dsr_region *r);
 
 /* ---- footprint and occupancy model ------------------------------------------
  * How many teams a compute unit holds at once, and what limits it, from

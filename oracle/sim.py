@@ -924,3 +924,35 @@ def fma_chain_init(s_i32, s_f64, arr=None):
 
 def gather_init(arrays):
     return b"".join(np.asarray(a, np.int32).tobytes() for a in arrays)
+
+
+# ---- served requests sized to their stacks (section 7) -------------------
+# Section 7 proposes to size a team's shared memory to what the kernel needs
+# instead of preallocating one size for every case.  A server that runs
+# resident teams of a few LDS sizes ("classes") does this per request: the
+# request goes to the smallest class whose on-chip stack holds every frame
+# the request pushes; a request no class holds goes to the largest, where
+# the frames that do not fit take the global-memory stack as usual.
+def stack_peak(program, align=8):
+    """Bytes a region's program holds on its stack at the most, every frame
+    rounded up to `align`: the largest sum of the live frames' sizes over
+    the program's pushes and pops (LIFO)."""
+    live, cur, peak = [], 0, 0
+    for op in program:
+        if isinstance(op, Push):
+            live.append(round_up(op.nbytes, align))
+            cur += live[-1]
+            peak = max(peak, cur)
+        elif isinstance(op, Pop):
+            cur -= live.pop()
+    return peak
+
+
+def lds_class(program, slabs, align=8):
+    """Index in `slabs` (on-chip stack bytes per class, any order) of the
+    class a request with this program is admitted to."""
+    need = stack_peak(program, align)
+    fits = [k for k, s in enumerate(slabs) if s >= need]
+    if fits:
+        return min(fits, key=lambda k: (slabs[k], k))
+    return max(range(len(slabs)), key=lambda k: (slabs[k], -k))

@@ -28,6 +28,12 @@ constexpr uint32_t kDefaultLdsPerWg = 160 * 1024;  /* gfx950 */
 
 }  // namespace
 
+struct dsr_region;
+namespace {
+bool stack_peaks(const dsr_region *r, uint32_t lds_cap, uint32_t threshold, uint64_t hbm_cap,
+                 uint64_t *lds_peak, uint64_t *hbm_peak);
+}  // namespace
+
 struct dsr_ctx {
     int device;                 /* -1: host-only context (validation only) */
     dsr_config cfg;
@@ -69,6 +75,7 @@ struct dsr_region {
     bool have_result;
     dsr_dregion static_desc;            /* descriptor copied into the workspace by
                                            dsr_launch_static */
+    dsr_dregion desc;                   /* host copy of the device descriptor */
 };
 
 extern "C" const char *dsr_strerror(int code)
@@ -266,6 +273,7 @@ static int prepare_loop(const dsr_region *r, const dsr_loop &L, const int32_t *f
     dl.block = block;
     dl.depth = L.depth;
     dl.dyn_start = dyn_start;
+    dl.deref = L.deref ? 1u : 0u;
     *out = dl;
     return DSR_OK;
 }
@@ -307,6 +315,7 @@ extern "C" int dsr_publish(dsr_region *r, int32_t frame, int32_t body, const dsr
     if (depth < 0) return DSR_E_STATE;
     if (r->loops.size() >= DSR_MAX_LOOPS || r->ops.size() >= DSR_MAX_OPS) return DSR_E_INVAL;
     const dsr_loop L = *loop;
+    if (L.deref) return DSR_E_INVAL;               /* a list publish only */
     const uint32_t nb = r->nbytes[frame];
     dsr_dloop dl{};
     int rc = prepare_loop(r, L, &frame, 1, &dl);
@@ -374,6 +383,7 @@ extern "C" int dsr_publish_list(dsr_region *r, const dsr_ref *refs, int32_t n, i
     if (r->loops.size() >= DSR_MAX_LOOPS || r->ops.size() >= DSR_MAX_OPS) return DSR_E_INVAL;
     const dsr_loop L = *loop;
     if (L.ni + L.nf > 64) return DSR_E_INVAL;
+    if (L.deref && L.alen) return DSR_E_INVAL;      /* per-batch reads: scalars only */
     if (n != (int32_t)(1 + L.ni + L.nf + (L.alen ? 1 : 0))) return DSR_E_INVAL;
     if (L.n && !L.in) return DSR_E_INVAL;
     std::vector<uint32_t> table(2 * (size_t)n);
@@ -489,7 +499,33 @@ static int upload(dsr_region *r)
     R.n_loops = (uint32_t)r->loops.size();
     if (hipMalloc((void **)&r->d_self, sizeof(dsr_dregion)) != hipSuccess) return DSR_E_NOMEM;
     if ((rc = hip_ok(hipMemcpy(r->d_self, &R, sizeof(R), hipMemcpyHostToDevice)))) return rc;
+    r->desc = R;
     return DSR_OK;
+}
+
+/* A single-region launch carries the region's descriptor R (device
+ * pointers) by value and, when its program is short, the program, its
+ * first loop and the image of the frame op 0 pushes. */
+static void fill_single(dsr_dlaunch &LP, const dsr_region *r, const dsr_dregion &R)
+{
+    LP.has_single = 1;
+    LP.single = R;
+    LP.inl_ops = LP.inl_loop = LP.inl_img = 0;
+    if (r->ops.empty() || r->ops.size() > DSR_INLINE_OPS) return;
+    LP.inl_ops = (uint32_t)r->ops.size();
+    std::memcpy(LP.inl_op, r->ops.data(), r->ops.size() * sizeof(dsr_op));
+    if (!r->loops.empty()) {
+        LP.inl_loop = 1;
+        LP.inl_loop0 = r->loops[0];
+    }
+    const dsr_op &op = r->ops[0];
+    if (op.kind == DSR_OP_PUSH && op.init_stride == 0 && op.init_bytes > 0 && op.init_bytes <= DSR_INLINE_IMG &&
+        op.init_off + op.init_bytes <= r->init.size()) {
+        const uint32_t padded = (op.init_bytes + 15u) & ~15u;
+        std::memset(LP.inl_image, 0, padded);
+        std::memcpy(LP.inl_image, r->init.data() + op.init_off, op.init_bytes);
+        LP.inl_img = padded;
+    }
 }
 
 static dsr_dconfig make_dconfig(const dsr_ctx *c, uint32_t wg, uint32_t lds_slab, uint32_t threshold,
@@ -527,6 +563,7 @@ extern "C" int dsr_launch(dsr_region *r, void *stream)
     LP.regions = r->d_self;
     LP.items = nullptr;
     LP.n_regions = 1;
+    fill_single(LP, r, r->desc);
     const dsr_dconfig C = make_dconfig(c, c->cfg.wg_size, c->cfg.lds_slab_bytes, c->cfg.overflow_threshold,
                                        c->cfg.master_joins, (c->cfg.flags & DSR_F_TRACE) ? 1u : 0u);
     /* events only when timing is asked for: a marker between back-to-back
@@ -706,6 +743,7 @@ extern "C" int dsr_launch_static(dsr_region *r, dsr_result_rec *result, void *st
     LP.regions = (const dsr_dregion *)(ws + L.desc);
     LP.items = nullptr;
     LP.n_regions = 1;
+    fill_single(LP, r, R);
     dsr_dconfig C = make_dconfig(c, c->cfg.wg_size, c->cfg.lds_slab_bytes, c->cfg.overflow_threshold,
                                  c->cfg.master_joins, 0u);
     C.hbm_base = ws + L.hbm;
@@ -730,6 +768,7 @@ struct dsr_batch {
     std::vector<int32_t> teams;
     std::vector<uint32_t> n_red;
     std::vector<std::vector<dsr_dloop>> loops;   /* host copies, for tune checks */
+    std::vector<uint32_t> stack_peak;            /* per region: its stack's peak bytes */
     std::vector<dsr_dresult> h_results;
     bool have_results;
     uint32_t variant;
@@ -815,6 +854,7 @@ extern "C" int dsr_batch_create(dsr_ctx *ctx, dsr_region *const *regions, int32_
         b->teams.resize(n);
         b->n_red.resize(n);
         b->loops.resize(n);
+        b->stack_peak.resize(n);
         b->h_results.resize(n);
     } catch (...) {
         delete b;
@@ -846,6 +886,9 @@ extern "C" int dsr_batch_create(dsr_ctx *ctx, dsr_region *const *regions, int32_
         b->n_red[i] = r->n_red;
         b->loops[i] = r->loops;
         b->variant = std::max(b->variant, r->variant);
+        uint64_t lp = 0, hp = 0;
+        (void)stack_peaks(r, 0xFFFFFFFFu, 0xFFFFFFFFu, ~0ull, &lp, &hp);
+        b->stack_peak[i] = (uint32_t)std::min<uint64_t>(lp + hp, 0xFFFFFFFFull);
     }
     uint32_t *it = (uint32_t *)(stage.data() + o_items);
     for (size_t k = 0; k < items.size(); ++k) { it[2 * k] = items[k].r; it[2 * k + 1] = items[k].t; }
@@ -1069,6 +1112,74 @@ extern "C" int dsr_batch_free(dsr_batch *b)
     return DSR_OK;
 }
 
+/* The occupancy model's parameters for `device` (gfx950: 4 SIMDs, each
+ * with 512 VGPRs (arch + acc) per lane, allocated in 8s). */
+static int device_model(int device, dsr_hw_model *hw)
+{
+    hipDeviceProp_t p{};
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return DSR_E_HIP;
+    if (p.multiProcessorCount <= 0 || p.maxThreadsPerMultiProcessor <= 0 || p.warpSize <= 0) return DSR_E_HIP;
+    const uint32_t wave = (uint32_t)p.warpSize, thr = (uint32_t)p.maxThreadsPerMultiProcessor;
+    *hw = dsr_hw_model{(uint32_t)p.multiProcessorCount, 4u * 512u * wave, 8u, thr / wave, thr,
+                       (uint32_t)p.maxSharedMemoryPerMultiProcessor, 128u, 4u, wave};
+    return DSR_OK;
+}
+
+extern "C" int dsr_autotune_plan(dsr_batch *b, dsr_tune *out, int32_t max, int32_t *n_out)
+{
+    if (!b || !n_out || max < 0 || (max > 0 && !out)) return DSR_E_INVAL;
+    *n_out = 0;
+    dsr_hw_model hw{};
+    int rc = device_model(b->ctx->device, &hw);
+    if (rc) return rc;
+    /* stack sizes the batch's frames ask for: the peaks at the median, the
+     * 90th, 99th percentile and the largest, rounded up to 1 KiB */
+    std::vector<uint32_t> peaks = b->stack_peak;
+    std::sort(peaks.begin(), peaks.end());
+    std::vector<uint32_t> slabs;
+    for (double q : {0.5, 0.9, 0.99, 1.0}) {
+        const uint32_t v = peaks.empty() ? 0u : peaks[std::min(peaks.size() - 1, (size_t)(q * (peaks.size() - 1)))];
+        slabs.push_back(std::max(1024u, (v + 1023u) & ~1023u));
+    }
+    struct cand { dsr_tune t; uint32_t waves; };
+    std::vector<cand> keep;
+    for (uint32_t wg : {64u, 128u, 256u, 512u, 1024u}) {
+        const uint32_t nw = wg / 64;
+        const uint32_t variant = wg > 256 ? 0 : b->variant;
+        const int regs = dsr_region_kernel_regs(wg, variant);
+        if (regs <= 0) continue;
+        /* per occupancy the largest slab: it keeps more frames on chip at
+         * no cost in resident teams */
+        std::vector<std::pair<uint32_t, uint32_t>> best;   /* (teams per CU, slab) */
+        for (uint32_t slab : slabs) {
+            const uint32_t room = b->lds_max > dsr::cb_bytes(nw) ? b->lds_max - dsr::cb_bytes(nw) : 0u;
+            const uint32_t sl = std::min(slab, room & ~15u);
+            dsr_occupancy o{};
+            if (dsr_occupancy_model(&hw, wg, (uint32_t)regs, dsr::cb_bytes(nw) + sl, &o) || o.teams_per_cu == 0)
+                continue;
+            bool placed = false;
+            for (auto &e : best)
+                if (e.first == o.teams_per_cu) { e.second = std::max(e.second, sl); placed = true; }
+            if (!placed) best.push_back({o.teams_per_cu, sl});
+        }
+        for (const auto &e : best)
+            for (uint32_t joins : {0u, 1u}) {
+                if ((nw == 1 && !joins) || (nw > 8 && joins)) continue;
+                const uint32_t working = joins ? nw : nw - 1;
+                cand c;
+                c.t = dsr_tune{wg, e.second, 0u, joins, 0u, 1u};
+                c.waves = e.first * working;
+                keep.push_back(c);
+            }
+    }
+    /* most working waves resident per CU first */
+    std::stable_sort(keep.begin(), keep.end(), [](const cand &a, const cand &c) { return a.waves > c.waves; });
+    const int32_t n = std::min<int32_t>(max, (int32_t)keep.size());
+    for (int32_t k = 0; k < n; ++k) out[k] = keep[k].t;
+    *n_out = (int32_t)keep.size();
+    return DSR_OK;
+}
+
 extern "C" int dsr_autotune(dsr_batch *b, const dsr_tune *cand, int32_t n_cand, int32_t reps, void *stream,
                             dsr_tune *best, float *ms)
 {
@@ -1115,7 +1226,8 @@ struct serve_slot {
     dsr_dresult *d_result;  /* device */
     bool busy;
     uint64_t ticket;
-    uint32_t first_item;
+    uint32_t first_item;    /* in its class's item ring */
+    uint32_t cls;           /* LDS class running the request */
     uint64_t lds_cost, hbm_cost;
 };
 
@@ -1158,33 +1270,84 @@ bool stack_peaks(const dsr_region *r, uint32_t lds_cap, uint32_t threshold, uint
 
 }  // namespace
 
+/* One LDS class of the server: a resident grid whose teams have `slab`
+ * bytes of on-chip stack, with its own item ring, published count, close
+ * handshake and stream.  Slots, completion records and tickets are shared
+ * by every class. */
+struct serve_class {
+    uint32_t slab, grid, lds_bytes, first_wg;
+    uint8_t *h_ctl;                   /* host-coherent: published, closing, final
+                                         count, start/exit flags, item ring     */
+    uint32_t *published;
+    uint32_t *closing;                /* device: the class is closing           */
+    uint32_t *final_items;            /* device: 1 + items served (0 = open)    */
+    uint32_t *wg_started;             /* per resident workgroup                 */
+    uint32_t *wg_exited;
+    uint32_t *items;
+    uint32_t *d_counter;              /* device control words                   */
+    uint32_t pub;
+    uint64_t lds_budget, lds_used;
+    hipStream_t stream;
+};
+
 struct dsr_server {
     dsr_ctx *ctx;
     dsr_serve_cfg cfg;
-    uint8_t *h_block;                 /* host-coherent control block         */
-    uint32_t *published;
+    uint8_t *h_block;                 /* host-coherent: stop, start ticks,
+                                         slot descriptors, completion records  */
     uint32_t *stop;
-    uint32_t *closing;                /* device: the server is closing        */
-    uint32_t *final_items;            /* device: 1 + items served (0 = open)  */
-    uint32_t *wg_started;             /* per resident workgroup               */
-    uint32_t *wg_exited;
     uint64_t *start_ticks;
-    uint32_t *items;
     dsr_dregion *regs;
     dsr_drec *recs;
     uint8_t *h_arena;                 /* host-coherent slot arenas            */
-    uint8_t *d_arena;                 /* device: partials, results, counter  */
-    uint32_t *d_counter;
+    uint8_t *d_arena;                 /* device: partials, results, counters  */
     std::vector<serve_slot> slots;
     std::vector<uint32_t> free_slots;
-    uint32_t pub;
+    std::vector<serve_class> cls;
     uint64_t next_ticket;
-    uint64_t lds_budget, hbm_budget, lds_used, hbm_used;
-    uint32_t grid, variant, lds_bytes;
+    uint64_t hbm_budget, hbm_used;
+    uint32_t variant;
     dsr_tune tune;
-    hipStream_t stream;
     uint32_t in_flight;
 };
+
+namespace {
+
+void serve_free(dsr_server *S)
+{
+    for (serve_class &k : S->cls) {
+        if (k.stream) (void)hipStreamDestroy(k.stream);
+        if (k.h_ctl) (void)hipHostFree(k.h_ctl);
+    }
+    if (S->d_arena) (void)hipFree(S->d_arena);
+    if (S->h_arena) (void)hipHostFree(S->h_arena);
+    if (S->h_block) (void)hipHostFree(S->h_block);
+    delete S;
+}
+
+/* Bytes of a region's stack at the most with every frame on chip (each
+ * frame rounded to the kernel's 16 bytes). */
+uint64_t full_stack(const dsr_region *r)
+{
+    uint64_t lp = 0, hp = 0;
+    (void)stack_peaks(r, 0xFFFFFFFFu, 0xFFFFFFFFu, ~0ull, &lp, &hp);
+    return lp;
+}
+
+}  // namespace
+
+extern "C" int dsr_serve_class_for(const uint32_t *slabs, int32_t n, const dsr_region *r)
+{
+    if (!slabs || n < 1 || n > DSR_SERVE_CLASSES || !r) return DSR_E_INVAL;
+    const uint64_t need = full_stack(r);
+    int32_t best = -1;
+    for (int32_t k = 0; k < n; ++k)
+        if (slabs[k] >= need && (best < 0 || slabs[k] < slabs[best])) best = k;
+    if (best >= 0) return best;
+    for (int32_t k = 0; k < n; ++k)
+        if (best < 0 || slabs[k] > slabs[best]) best = k;
+    return best;
+}
 
 extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_server **out)
 {
@@ -1198,6 +1361,7 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
     if ((uint64_t)c.slots * c.max_teams > c.ring_items) return DSR_E_INVAL;
     if (c.idle_ms == 0) c.idle_ms = 10000;
     if (c.budget_pct == 0 || c.budget_pct > 100) c.budget_pct = 100;
+    if (c.n_classes > DSR_SERVE_CLASSES) return DSR_E_INVAL;
     dsr_tune t = c.tune;
     if (t.wg_size < 64 || t.wg_size > 1024 || (t.wg_size & 63u) || (t.lds_slab_bytes & 15u)) return DSR_E_INVAL;
     const uint32_t nw = t.wg_size / 64;
@@ -1209,74 +1373,89 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
         lds_max = (uint32_t)v;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && v > 0)
         cus = (uint32_t)v;
-    const uint64_t lds = (uint64_t)dsr::cb_bytes(nw) + t.lds_slab_bytes + DSR_SERVE_LDS_BYTES;
-    if (lds > lds_max) return DSR_E_LDS;
     const uint32_t variant = 0;
-    uint32_t grid = t.grid;
-    if (grid == 0) {
-        const int occ = dsr_region_kernel_occupancy(t.wg_size, (uint32_t)lds, variant);
-        if (occ <= 0) return DSR_E_LDS;
-        grid = std::min((uint32_t)occ * cus, ctx->cfg.max_teams);
+    /* the classes: one of the tune's slab and grid, or those given */
+    const uint32_t n_cls = c.n_classes ? c.n_classes : 1u;
+    std::vector<serve_class> cls(n_cls);
+    uint32_t grid_total = 0;
+    for (uint32_t k = 0; k < n_cls; ++k) {
+        serve_class &K = cls[k];
+        K = serve_class{};
+        K.slab = c.n_classes ? c.class_slab[k] : t.lds_slab_bytes;
+        if (K.slab & 15u) return DSR_E_INVAL;
+        const uint64_t lds = (uint64_t)dsr::cb_bytes(nw) + K.slab + DSR_SERVE_LDS_BYTES;
+        if (lds > lds_max) return DSR_E_LDS;
+        K.lds_bytes = (uint32_t)lds;
+        uint32_t grid = c.n_classes ? c.class_grid[k] : t.grid;
+        if (grid == 0) {
+            /* as many as fit less one workgroup slot per CU (one CU per 32
+             * when only one fits), shared evenly between the classes.  The
+             * runtime runs its copies as kernels of its own: with every
+             * slot held by the resident grid a copy issued meanwhile, on
+             * any stream, waits until the server closes (measured: a
+             * device-to-host copy blocked for the whole idle limit at full
+             * occupancy and took 0.6 ms with one slot per CU free). */
+            const int occ = dsr_region_kernel_occupancy(t.wg_size, K.lds_bytes, variant);
+            if (occ <= 0) return DSR_E_LDS;
+            const uint32_t slots_all = (uint32_t)occ * cus;
+            const uint32_t spare = occ >= 2 ? cus : std::max(1u, cus / 32);
+            grid = std::max(1u, (slots_all > spare ? slots_all - spare : 1u) / n_cls);
+        }
+        K.grid = grid;
+        K.first_wg = grid_total;
+        grid_total += grid;
     }
-    if (grid > ctx->cfg.max_teams) return DSR_E_NOMEM;
-    t.grid = grid;
+    if (grid_total > ctx->cfg.max_teams) return DSR_E_NOMEM;
+    t.grid = cls[0].grid;
 
     dsr_server *S = new (std::nothrow) dsr_server();
     if (!S) return DSR_E_NOMEM;
     S->ctx = ctx;
     S->cfg = c;
     S->tune = t;
-    S->grid = grid;
     S->variant = variant;
-    S->lds_bytes = (uint32_t)lds;
-    S->pub = 0;
     S->next_ticket = 1;
     S->in_flight = 0;
-    S->lds_used = S->hbm_used = 0;
-    S->lds_budget = (uint64_t)grid * t.lds_slab_bytes * c.budget_pct / 100;
-    S->hbm_budget = (uint64_t)grid * ctx->cfg.hbm_slab_bytes * c.budget_pct / 100;
-    /* host-coherent control block: published, stop, start ticks, closing,
-     * final count, per-workgroup start and exit flags, item ring, region
-     * descriptors, completion records */
-    const size_t o_wg = 512, o_items = o_wg + 2 * align256((size_t)grid * 4);
-    const size_t o_regs = o_items + align256((size_t)c.ring_items * 8);
+    S->hbm_used = 0;
+    S->hbm_budget = (uint64_t)grid_total * ctx->cfg.hbm_slab_bytes * c.budget_pct / 100;
+    S->cls = cls;
+    for (serve_class &K : S->cls) {
+        K.lds_used = 0;
+        K.lds_budget = (uint64_t)K.grid * K.slab * c.budget_pct / 100;
+    }
+    /* shared host-coherent block: stop, start ticks, slot descriptors,
+     * completion records */
+    const size_t o_regs = 512;
     const size_t o_recs = o_regs + align256((size_t)c.slots * sizeof(dsr_dregion));
     const size_t blk = o_recs + align256((size_t)c.slots * sizeof(dsr_drec));
     const size_t slot_h = align256(DSR_SERVE_MAX_OPS * sizeof(dsr_op)) +
                           align256(DSR_SERVE_MAX_LOOPS * sizeof(dsr_dloop)) + align256(c.slot_bytes);
     const size_t part_b = align256((size_t)DSR_MAX_RED * c.max_teams * DSR_PART_WORDS * sizeof(uint64_t));
     const size_t slot_d = part_b + align256(sizeof(dsr_dresult));
+    const size_t ctl_d = DSR_SRV_WORDS * sizeof(uint32_t);
     if (hipSetDevice(ctx->device) != hipSuccess) { delete S; return DSR_E_HIP; }
     if (hipHostMalloc((void **)&S->h_block, blk, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
-        delete S;
+        serve_free(S);
         return DSR_E_NOMEM;
     }
     std::memset(S->h_block, 0, blk);
     if (hipHostMalloc((void **)&S->h_arena, slot_h * c.slots, hipHostMallocCoherent | hipHostMallocMapped) !=
         hipSuccess) {
-        (void)hipHostFree(S->h_block);
-        delete S;
+        serve_free(S);
         return DSR_E_NOMEM;
     }
-    const size_t ctl_d = DSR_SRV_WORDS * sizeof(uint32_t);
-    if (hipMalloc((void **)&S->d_arena, slot_d * c.slots + ctl_d) != hipSuccess ||
-        hipMemset(S->d_arena, 0, slot_d * c.slots + ctl_d) != hipSuccess) {
-        (void)hipHostFree(S->h_arena);
-        (void)hipHostFree(S->h_block);
-        delete S;
+    /* device arena: slot partials and results, then each class's control
+     * words, cleared before any class's kernel can run */
+    const size_t d_bytes = slot_d * c.slots + ctl_d * n_cls;
+    if (hipMalloc((void **)&S->d_arena, d_bytes) != hipSuccess || hipMemset(S->d_arena, 0, d_bytes) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        serve_free(S);
         return DSR_E_NOMEM;
     }
-    S->published = (uint32_t *)S->h_block;
     S->stop = (uint32_t *)(S->h_block + 64);
     S->start_ticks = (uint64_t *)(S->h_block + 128);
-    S->closing = (uint32_t *)(S->h_block + 192);
-    S->final_items = (uint32_t *)(S->h_block + 256);
-    S->wg_started = (uint32_t *)(S->h_block + o_wg);
-    S->wg_exited = (uint32_t *)(S->h_block + o_wg + align256((size_t)grid * 4));
-    S->items = (uint32_t *)(S->h_block + o_items);
     S->regs = (dsr_dregion *)(S->h_block + o_regs);
     S->recs = (dsr_drec *)(S->h_block + o_recs);
-    S->d_counter = (uint32_t *)(S->d_arena + slot_d * c.slots);
     S->slots.resize(c.slots);
     for (uint32_t i = 0; i < c.slots; ++i) {
         uint8_t *h = S->h_arena + slot_h * i;
@@ -1287,40 +1466,62 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
         sl.d_partials = (uint64_t *)(S->d_arena + slot_d * i);
         sl.d_result = (dsr_dresult *)(S->d_arena + slot_d * i + part_b);
         sl.busy = false;
+        sl.cls = 0;
         S->free_slots.push_back(c.slots - 1 - i);
     }
-    if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipFree(S->d_arena);
-        (void)hipHostFree(S->h_arena);
-        (void)hipHostFree(S->h_block);
-        delete S;
-        return DSR_E_HIP;
+    for (uint32_t k = 0; k < n_cls; ++k) {
+        serve_class &K = S->cls[k];
+        /* per class, host-coherent: published, closing, final count,
+         * workgroup start and exit flags, item ring */
+        const size_t o_wg = 256, o_items = o_wg + 2 * align256((size_t)K.grid * 4);
+        const size_t ctl = o_items + align256((size_t)c.ring_items * 8);
+        if (hipHostMalloc((void **)&K.h_ctl, ctl, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+            serve_free(S);
+            return DSR_E_NOMEM;
+        }
+        std::memset(K.h_ctl, 0, ctl);
+        K.published = (uint32_t *)K.h_ctl;
+        K.closing = (uint32_t *)(K.h_ctl + 64);
+        K.final_items = (uint32_t *)(K.h_ctl + 128);
+        K.wg_started = (uint32_t *)(K.h_ctl + o_wg);
+        K.wg_exited = (uint32_t *)(K.h_ctl + o_wg + align256((size_t)K.grid * 4));
+        K.items = (uint32_t *)(K.h_ctl + o_items);
+        K.d_counter = (uint32_t *)(S->d_arena + slot_d * c.slots + ctl_d * k);
+        K.pub = 0;
+        if (hipStreamCreateWithFlags(&K.stream, hipStreamNonBlocking) != hipSuccess) {
+            serve_free(S);
+            return DSR_E_HIP;
+        }
     }
-    dsr_dlaunch LP{};
-    LP.regions = S->regs;
-    LP.items = S->items;
-    LP.n_items = 0;
-    LP.n_regions = c.slots;
-    LP.counter = S->d_counter;
-    LP.done_ts = S->start_ticks;
-    LP.published = S->published;
-    LP.stop = S->stop;
-    LP.recs = S->recs;
-    LP.ring_mask = c.ring_items - 1;
-    LP.idle_limit = (uint64_t)c.idle_ms * 100000ull;
-    LP.closing = S->closing;
-    LP.final_items = S->final_items;
-    LP.wg_started = S->wg_started;
-    LP.wg_exited = S->wg_exited;
-    dsr_dconfig C = make_dconfig(ctx, t.wg_size, t.lds_slab_bytes, t.overflow_threshold, t.master_joins, 0);
-    C.serve = 1;
-    if (dsr_launch_region_kernel(&LP, &C, grid, t.wg_size, S->lds_bytes, variant, S->stream) != 0) {
-        (void)hipStreamDestroy(S->stream);
-        (void)hipFree(S->d_arena);
-        (void)hipHostFree(S->h_arena);
-        (void)hipHostFree(S->h_block);
-        delete S;
-        return DSR_E_HIP;
+    for (uint32_t k = 0; k < n_cls; ++k) {
+        serve_class &K = S->cls[k];
+        dsr_dlaunch LP{};
+        LP.regions = S->regs;
+        LP.items = K.items;
+        LP.n_items = 0;
+        LP.n_regions = c.slots;
+        LP.counter = K.d_counter;
+        LP.done_ts = k == 0 ? S->start_ticks : nullptr;
+        LP.published = K.published;
+        LP.stop = S->stop;
+        LP.recs = S->recs;
+        LP.ring_mask = c.ring_items - 1;
+        LP.idle_limit = (uint64_t)c.idle_ms * 100000ull;
+        LP.closing = K.closing;
+        LP.final_items = K.final_items;
+        LP.wg_started = K.wg_started;
+        LP.wg_exited = K.wg_exited;
+        dsr_dconfig C = make_dconfig(ctx, t.wg_size, K.slab, t.overflow_threshold, t.master_joins, 0);
+        C.serve = 1;
+        /* each class's teams take their own HBM stack and nested slots */
+        C.hbm_base = ctx->hbm + (uint64_t)K.first_wg * ctx->cfg.hbm_slab_bytes;
+        C.nest_base = ctx->nest + (uint64_t)K.first_wg * DSR_NEST_SLOT;
+        if (dsr_launch_region_kernel(&LP, &C, K.grid, t.wg_size, K.lds_bytes, variant, K.stream) != 0) {
+            __atomic_store_n(S->stop, 1u, __ATOMIC_RELEASE);
+            for (uint32_t j = 0; j < k; ++j) (void)hipStreamSynchronize(S->cls[j].stream);
+            serve_free(S);
+            return DSR_E_HIP;
+        }
     }
     *out = S;
     return DSR_OK;
@@ -1331,7 +1532,7 @@ static void serve_release(dsr_server *S, uint32_t k)
 {
     serve_slot &sl = S->slots[k];
     sl.busy = false;
-    S->lds_used -= sl.lds_cost;
+    S->cls[sl.cls].lds_used -= sl.lds_cost;
     S->hbm_used -= sl.hbm_cost;
     S->in_flight--;
     S->free_slots.push_back(k);
@@ -1342,8 +1543,6 @@ extern "C" int dsr_serve_submit(dsr_server *S, dsr_region *r, void *const *outs,
 {
     if (!S || !r || !ticket || n_outs < 0) return DSR_E_INVAL;
     if (r->ctx != S->ctx) return DSR_E_INVAL;
-    /* the server closed (stop, or no new work for idle_ms) */
-    if (__atomic_load_n(S->closing, __ATOMIC_SEQ_CST) != 0) return DSR_E_STATE;
     if (!r->live.empty()) return DSR_E_LIVE;
     if (r->ops.size() > DSR_SERVE_MAX_OPS || r->loops.size() > DSR_SERVE_MAX_LOOPS) return DSR_E_INVAL;
     if ((uint32_t)r->teams > S->cfg.max_teams || r->init.size() > S->cfg.slot_bytes) return DSR_E_INVAL;
@@ -1352,18 +1551,49 @@ extern "C" int dsr_serve_submit(dsr_server *S, dsr_region *r, void *const *outs,
     const uint64_t lanes = 64ull * (S->tune.master_joins ? S->tune.wg_size / 64 : S->tune.wg_size / 64 - 1);
     for (const dsr_dloop &L : r->loops)
         if ((L.chunk + lanes - 1) / lanes > (1ull << 15)) return DSR_E_INVAL;
-    uint64_t lp = 0, hp = 0;
+    /* the class sized to the request's stack; a class that has closed
+     * (stop, or idle) is passed over for the next larger one still open */
+    uint32_t slabs[DSR_SERVE_CLASSES];
+    const int32_t n_cls = (int32_t)S->cls.size();
+    for (int32_t k = 0; k < n_cls; ++k) slabs[k] = S->cls[k].slab;
+    std::vector<int32_t> order;
+    const int32_t first = dsr_serve_class_for(slabs, n_cls, r);
+    order.push_back(first);
+    for (int32_t k = 0; k < n_cls; ++k)
+        if (k != first && slabs[k] >= slabs[first]) order.push_back(k);
+    std::sort(order.begin() + 1, order.end(), [&](int32_t a, int32_t b) { return slabs[a] < slabs[b]; });
+    for (int32_t k = 0; k < n_cls; ++k)
+        if (std::find(order.begin(), order.end(), k) == order.end()) order.push_back(k);
+    int32_t kc = -1;
+    bool busy = false;
+    uint64_t lcost = 0, hcost = 0;
     const uint32_t thr = S->tune.overflow_threshold ? S->tune.overflow_threshold : 0xFFFFFFFFu;
-    if (!stack_peaks(r, S->tune.lds_slab_bytes, thr, S->ctx->cfg.hbm_slab_bytes, &lp, &hp)) return DSR_E_NOMEM;
-    const uint64_t lcost = lp * r->teams, hcost = hp * r->teams;
+    for (int32_t k : order) {
+        serve_class &K = S->cls[k];
+        if (__atomic_load_n(K.closing, __ATOMIC_SEQ_CST) != 0) continue;
+        uint64_t lp = 0, hp = 0;
+        if (!stack_peaks(r, K.slab, thr, S->ctx->cfg.hbm_slab_bytes, &lp, &hp)) return DSR_E_NOMEM;
+        const uint64_t lc = lp * r->teams, hc = hp * r->teams;
+        /* ring space: items of the oldest unfinished request bound the writer */
+        uint32_t floor_item = K.pub;
+        for (const serve_slot &sl : S->slots)
+            if (sl.busy && sl.cls == (uint32_t)k && (int32_t)(sl.first_item - floor_item) < 0)
+                floor_item = sl.first_item;
+        const bool fits = (!S->in_flight || (K.lds_used + lc <= K.lds_budget && S->hbm_used + hc <= S->hbm_budget)) &&
+                          K.pub + (uint32_t)r->teams - floor_item <= S->cfg.ring_items;
+        if (!fits) {
+            busy = true;
+            /* a larger class takes it only while the sized one is full */
+            continue;
+        }
+        kc = k;
+        lcost = lc;
+        hcost = hc;
+        break;
+    }
+    if (kc < 0) return busy ? DSR_E_BUSY : DSR_E_STATE;
     if (S->free_slots.empty()) return DSR_E_BUSY;
-    if (S->in_flight && (S->lds_used + lcost > S->lds_budget || S->hbm_used + hcost > S->hbm_budget))
-        return DSR_E_BUSY;
-    /* ring space: items of the oldest unfinished request bound the writer */
-    uint32_t floor_item = S->pub;
-    for (const serve_slot &sl : S->slots)
-        if (sl.busy && (int32_t)(sl.first_item - floor_item) < 0) floor_item = sl.first_item;
-    if (S->pub + (uint32_t)r->teams - floor_item > S->cfg.ring_items) return DSR_E_BUSY;
+    serve_class &K = S->cls[kc];
 
     const uint32_t k = S->free_slots.back();
     S->free_slots.pop_back();
@@ -1390,33 +1620,34 @@ extern "C" int dsr_serve_submit(dsr_server *S, dsr_region *r, void *const *outs,
     R.n_loops = (uint32_t)r->loops.size();
     S->regs[k] = R;
     for (int32_t t = 0; t < r->teams; ++t) {
-        const uint32_t it = (S->pub + (uint32_t)t) & (S->cfg.ring_items - 1);
-        S->items[2 * it] = k;
-        S->items[2 * it + 1] = (uint32_t)t;
+        const uint32_t it = (K.pub + (uint32_t)t) & (S->cfg.ring_items - 1);
+        K.items[2 * it] = k;
+        K.items[2 * it + 1] = (uint32_t)t;
     }
     sl.busy = true;
     sl.ticket = tk;
-    sl.first_item = S->pub;
+    sl.first_item = K.pub;
+    sl.cls = (uint32_t)kc;
     sl.lds_cost = lcost;
     sl.hbm_cost = hcost;
-    S->lds_used += lcost;
+    K.lds_used += lcost;
     S->hbm_used += hcost;
     S->in_flight++;
-    S->pub += (uint32_t)r->teams;
+    K.pub += (uint32_t)r->teams;
     /* everything above is visible before the new count; then look for a
      * close the device may have begun meanwhile (its side writes the
      * closing flag, then reads the count: one of the two reads sees the
      * other side's write) */
-    __atomic_store_n(S->published, S->pub, __ATOMIC_SEQ_CST);
+    __atomic_store_n(K.published, K.pub, __ATOMIC_SEQ_CST);
     __atomic_thread_fence(__ATOMIC_SEQ_CST);
-    if (__atomic_load_n(S->closing, __ATOMIC_SEQ_CST) != 0) {
+    if (__atomic_load_n(K.closing, __ATOMIC_SEQ_CST) != 0) {
         /* the closing workgroup reports the count it read right away */
         uint32_t fin = 0;
         const auto t0 = std::chrono::steady_clock::now();
-        while ((fin = __atomic_load_n(S->final_items, __ATOMIC_ACQUIRE)) == 0) {
+        while ((fin = __atomic_load_n(K.final_items, __ATOMIC_ACQUIRE)) == 0) {
             if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(10)) return DSR_E_HIP;
         }
-        if ((int32_t)(S->pub - (fin - 1u)) > 0) {
+        if ((int32_t)(K.pub - (fin - 1u)) > 0) {
             /* published after the close: the device will not run it */
             serve_release(S, k);
             return DSR_E_STATE;
@@ -1448,6 +1679,7 @@ extern "C" int dsr_serve_poll(dsr_server *S, dsr_done *out, int32_t max)
         }
         const uint64_t t0 = __atomic_load_n(S->start_ticks, __ATOMIC_ACQUIRE);
         d.device_us = ((double)rec.ticks - (double)t0) / 100.0;
+        d.lds_class = (int32_t)sl.cls;
         serve_release(S, k);
     }
     return n;
@@ -1463,16 +1695,30 @@ extern "C" int dsr_serve_status(dsr_server *S, dsr_serve_stat *out)
 {
     if (!S || !out) return DSR_E_INVAL;
     dsr_serve_stat st{};
-    st.grid = S->grid;
-    for (uint32_t b = 0; b < S->grid; ++b) {
-        st.started += __atomic_load_n(S->wg_started + b, __ATOMIC_ACQUIRE) != 0;
-        st.exited += __atomic_load_n(S->wg_exited + b, __ATOMIC_ACQUIRE) != 0;
+    st.closed = 1;
+    for (const serve_class &K : S->cls) {
+        st.grid += K.grid;
+        for (uint32_t b = 0; b < K.grid; ++b) {
+            st.started += __atomic_load_n(K.wg_started + b, __ATOMIC_ACQUIRE) != 0;
+            st.exited += __atomic_load_n(K.wg_exited + b, __ATOMIC_ACQUIRE) != 0;
+        }
+        /* closed: every class has closed */
+        if (__atomic_load_n(K.closing, __ATOMIC_ACQUIRE) == 0) {
+            st.closed = 0;
+        } else if (!st.close_reason) {
+            const uint32_t *why = K.closing + 1;
+            st.close_reason = __atomic_load_n(why, __ATOMIC_ACQUIRE);
+            st.close_block = why[1];
+            st.close_item = why[2];
+            st.close_seen = why[3];
+            st.close_idle_us = (double)((uint64_t)why[4] | ((uint64_t)why[5] << 32)) / 100.0;
+        }
+        const uint32_t fin = __atomic_load_n(K.final_items, __ATOMIC_ACQUIRE);
+        st.final_items += fin ? fin - 1 : 0;
+        st.published += K.pub;
     }
-    st.closed = __atomic_load_n(S->closing, __ATOMIC_ACQUIRE) != 0;
-    const uint32_t fin = __atomic_load_n(S->final_items, __ATOMIC_ACQUIRE);
-    st.final_items = fin ? fin - 1 : 0;
-    st.published = S->pub;
     st.in_flight = S->in_flight;
+    st.classes = (uint32_t)S->cls.size();
     *out = st;
     return DSR_OK;
 }
@@ -1481,12 +1727,12 @@ extern "C" int dsr_serve_stop(dsr_server *S)
 {
     if (!S) return DSR_E_INVAL;
     __atomic_store_n(S->stop, 1u, __ATOMIC_RELEASE);
-    const hipError_t e = hipStreamSynchronize(S->stream);
-    (void)hipStreamDestroy(S->stream);
-    (void)hipFree(S->d_arena);
-    (void)hipHostFree(S->h_arena);
-    (void)hipHostFree(S->h_block);
-    delete S;
+    hipError_t e = hipSuccess;
+    for (serve_class &K : S->cls) {
+        const hipError_t ek = hipStreamSynchronize(K.stream);
+        if (ek != hipSuccess) e = ek;
+    }
+    serve_free(S);
     return e == hipSuccess ? DSR_OK : DSR_E_HIP;
 }
 

@@ -39,6 +39,8 @@ struct dsr_dloop {
     uint32_t ni, nf, alen, arrays;
     uint32_t len, schedule, block, depth;   /* depth: nested levels (nested body) */
     uint64_t dyn_start;    /* first iteration of the dynamic tail (= n if none) */
+    uint32_t deref;        /* list body: re-read the references every batch  */
+    uint32_t pad;
 };
 
 /* Per-launch result block (device memory, written by the last team). */
@@ -73,10 +75,15 @@ struct dsr_dregion {
     uint32_t pad;
 };
 
+/* Program parts a single-region launch carries in its kernel arguments. */
+#define DSR_INLINE_OPS 4
+#define DSR_INLINE_IMG 512
+
 /* Served form limits (a request's program is copied into LDS per item). */
 #define DSR_SERVE_MAX_OPS 16
 #define DSR_SERVE_MAX_LOOPS 4
 #define DSR_SERVE_LDS_BYTES (128 + DSR_SERVE_MAX_OPS * 48 + DSR_SERVE_MAX_LOOPS * 80)
+static_assert(sizeof(dsr_op) == 48 && sizeof(dsr_dloop) == 80, "served LDS copy layout");
 
 /* Served form: completion record of one request slot, in host-coherent
  * memory.  The device fills it and then stores `seq` (the request ticket)
@@ -117,19 +124,32 @@ struct dsr_dlaunch {
     uint32_t *wg_started;      /* host-coherent, per workgroup: 1 once it runs */
     uint32_t *wg_exited;       /* host-coherent, per workgroup: 1 once it left */
     uint64_t *start_ts;        /* if set, block 0 stamps its start time here */
-    uint64_t idle_limit;       /* close after this many ticks in which the
-                                  published count did not change            */
+    uint64_t idle_limit;       /* close after a waiting workgroup saw the
+                                  published count unchanged for this many
+                                  ticks of its own clock                    */
+    /* Single-region launches (items == null) may carry the region's
+     * descriptor by value and, for a program of at most DSR_INLINE_OPS ops,
+     * its ops, its first loop descriptor and the initial image of the frame
+     * its first op pushes (the same image for every team), so that a team
+     * forks without reading any of them from memory first. */
+    uint32_t has_single;       /* `single` holds regions[0]                 */
+    uint32_t inl_ops;          /* ops held in inl_op (0: read them from memory) */
+    uint32_t inl_loop;         /* inl_loop0 holds loop 0                    */
+    uint32_t inl_img;          /* image bytes held in inl_image (a multiple
+                                  of 16, zero-padded; 0: none)              */
+    dsr_dregion single;
+    dsr_dloop inl_loop0;
+    dsr_op inl_op[DSR_INLINE_OPS];
+    uint8_t inl_image[DSR_INLINE_IMG];
 };
 
 /* Served form: control words in device memory (LP.counter, 32-bit words).
  * The claim counter, the device copy of the host's published count, the
- * server state, the item count it serves before leaving, and the wall
- * clock of the last change of the published count (64-bit, two words). */
+ * server state and the item count it serves before leaving. */
 #define DSR_SRV_CLAIM 0
 #define DSR_SRV_PUB 16
 #define DSR_SRV_STATE 32      /* 0 open, 1 closing, 2 closed            */
 #define DSR_SRV_FINAL 48      /* valid once the state is 2              */
-#define DSR_SRV_LAST 64       /* uint64 at counter + 64                 */
 #define DSR_SRV_WORDS 128
 
 /* Launch-wide configuration. */

@@ -608,6 +608,30 @@ struct lane_scalars {
     }
 };
 
+/* The scalars read through the published reference list on every batch:
+ * each chain step reads reference 1 + k (a space and an offset), then the
+ * variable it names, as outlined code must when stores in its loop may
+ * alias the shared variables (section 5.1's sharing by reference).  The
+ * list is on chip or in a list frame on the HBM stack, the variables on
+ * either stack; all of it is read through generic pointers, as the outlined
+ * function receives them. */
+struct list_scalars {
+    const uint32_t *lst;
+    const uint8_t *stack_lds, *stack_hbm;
+    uint32_t ni, nf;
+
+    template <int E>
+    __device__ __forceinline__ void chain(double (&acc)[E], const double (&xd)[E]) const
+    {
+        for (uint32_t k = 0; k < ni + nf; ++k) {
+            const uint32_t sp = uniform(lst[2 * (1 + k)]), off = uniform(lst[2 * (1 + k) + 1]);
+            const uint8_t *p = (sp == SPACE_LDS ? stack_lds : stack_hbm) + off;
+            const double v = k < ni ? (double)*(const int32_t *)p : *(const double *)p;
+            fma_all<E>(v, acc, xd);
+        }
+    }
+};
+
 template <bool ARR, class AP, class SC>
 __device__ __forceinline__ double rt_one(const SC &sc, AP arr, uint32_t alen, double xd, uint64_t i)
 {
@@ -1027,6 +1051,9 @@ __device__ __forceinline__ void run_body(team_t &T, uint32_t body, frame_t f, co
     const uint32_t lane = T.lane;
     if constexpr (VARIANT >= DSR_LEAN_BASE) {
         /* the host dispatches only regions made of this chain here */
+        /* every scalar stays in registers: reading them once per batch
+         * instead (the general instances' run-time chain) measured slower
+         * here for every chain length */
         if (body == DSR_BODY_FMA_CHAIN)
             body_fma_fixed<lean_chain<VARIANT>::ni, lean_chain<VARIANT>::nf>(T, f, L, sp, A, claim, lane);
         return;
@@ -1073,15 +1100,20 @@ __device__ __forceinline__ void run_body(team_t &T, uint32_t body, frame_t f, co
             sv = lane < ni ? (double)*(const int32_t *)p : *(const double *)p;
         }
         /* with the counts of a compiled fixed chain, run that chain */
-        if (VARIANT >= 0 && alen == 0) {
+        if (VARIANT >= 0 && alen == 0 && !uniform(L.deref)) {
             if (ni == 1 && nf == 0) { lanes_fma_fixed<1, 0>(sv, L, sp, A, claim, lane); break; }
             if (ni == 1 && nf == 1) { lanes_fma_fixed<1, 1>(sv, L, sp, A, claim, lane); break; }
             if (ni == 2 && nf == 2) { lanes_fma_fixed<2, 2>(sv, L, sp, A, claim, lane); break; }
             if (ni == 4 && nf == 4) { lanes_fma_fixed<4, 4>(sv, L, sp, A, claim, lane); break; }
             if (ni == 8 && nf == 8) { lanes_fma_fixed<8, 8>(sv, L, sp, A, claim, lane); break; }
         }
-        const lane_scalars sc{sv, ni + nf};
         constexpr int U = VARIANT < 0 ? 1 : DSR_RT_PAIRS;
+        if (uniform(L.deref) && alen == 0) {
+            const list_scalars ls{lst, T.stack_lds, T.stack_hbm, ni, nf};
+            rt_spans<U>(ls, (const GLB int32_t *)nullptr, L, 0, sp, A, claim, lane);
+            break;
+        }
+        const lane_scalars sc{sv, ni + nf};
         if (alen) {
             const uint32_t asp = uniform(lst[2 * (1 + ni + nf)]), aoff = uniform(lst[2 * (1 + ni + nf) + 1]);
             if (asp == SPACE_LDS)
@@ -1146,10 +1178,9 @@ __device__ __forceinline__ span_t team_span(const dsr_dloop &L, uint32_t team, u
 template <int VARIANT>
 __device__ __forceinline__ void participate(team_t &T, const dsr_dregion &R, const dsr_dconfig &C,
                                             uint32_t team, uint32_t body, frame_t f, uint32_t loop,
-                                            uint32_t &inner_pushes)
+                                            const dsr_dloop &L, uint32_t &inner_pushes)
 {
     const uint32_t nwork = C.master_joins ? T.nw : T.nw - 1;
-    const dsr_dloop &L = R.loops[loop];
     lane_acc A = acc_zero();
     uint32_t *tr = (C.trace && R.trace) ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
     if (tr && T.lane == 0) tr[96 + 2 * T.wave] = (uint32_t)wall_clock64();
@@ -1255,6 +1286,36 @@ __device__ __forceinline__ dsr_op op_at(const op_lanes &o, uint32_t k)
     return op;
 }
 
+/* The region descriptor fields the arrival and the combine use, held in
+ * registers: read once before the arrival atomics, so no fence between
+ * them makes the last team reload the descriptor from memory. */
+struct region_sums {
+    uint64_t *partials;
+    dsr_dresult *result;
+    uint32_t teams, n_red, red_kind_mask;
+};
+
+__device__ __forceinline__ region_sums sums_of(const dsr_dregion &R)
+{
+    region_sums S;
+    S.partials = R.partials;
+    S.result = R.result;
+    S.teams = uniform(R.teams);
+    S.n_red = uniform(R.n_red);
+    S.red_kind_mask = uniform(R.red_kind_mask);
+    return S;
+}
+
+/* Master wave: this team's partial of one reduction (lane 0 stores). */
+__device__ __forceinline__ void store_partial(uint64_t *pp, i192 sv, uint32_t lane)
+{
+    if (lane == 0) {
+        store_dev(pp, sv.w0);
+        store_dev(pp + 1, sv.w1);
+        store_dev(pp + 2, sv.w2);
+    }
+}
+
 /* Master wave: add the join's total into the shared sum at c (an int64
  * for the integer body, else a 192-bit integer in 2^-75 units) and return
  * the new value as 192 bits. */
@@ -1283,8 +1344,8 @@ __device__ __forceinline__ i192 update_sum(P c, i192 tot, bool integer_sum, uint
  * (Figure 2): pushes, publishes and pops.  Returns the team's error. */
 template <int VARIANT>
 __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, const dsr_dconfig &C,
-                                               uint32_t region, uint32_t team, uint32_t &barriers,
-                                               uint32_t &inner_pushes)
+                                               const dsr_dlaunch &LP, bool single, uint32_t region,
+                                               uint32_t team, uint32_t &barriers, uint32_t &inner_pushes)
 {
     cb_header *h = header(T);
     uint32_t *tr = (C.trace && R.trace) ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
@@ -1295,11 +1356,20 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
     bool stamped = false;
     const uint32_t nwork = C.master_joins ? T.nw : T.nw - 1;
     const uint32_t n_ops = min(uniform(R.n_ops), (uint32_t)DSR_MAX_OPS);
+    /* read once, before any join: after a barrier the compiler would load
+     * them from memory again, behind this wave's outstanding stores */
+    const region_sums RS = sums_of(R);
+    /* a short program of a single-region launch, its first loop and its
+     * first frame's image come with the kernel arguments; the image is read
+     * into registers (16 bytes a lane) before anything else */
+    const bool inl = VARIANT >= DSR_LEAN_BASE && single && LP.inl_ops == n_ops && n_ops > 0;
+    i32x4 img = {0, 0, 0, 0};
+    if (inl && LP.inl_img && 16u * T.lane < LP.inl_img) img = *(const i32x4 *)(LP.inl_image + 16u * T.lane);
     /* the 1024-thread instance has no registers to spare: it reads each op
      * when it gets to it */
-    const op_lanes prog = load_ops(R.ops, VARIANT < 0 ? 0 : n_ops, T.lane);
+    const op_lanes prog = load_ops(R.ops, (VARIANT < 0 || inl) ? 0 : n_ops, T.lane);
     for (uint32_t k = 0; k < n_ops; ++k) {
-        const dsr_op op = VARIANT < 0 ? R.ops[k] : op_at(prog, k);
+        const dsr_op op = inl ? LP.inl_op[k] : (VARIANT < 0 ? R.ops[k] : op_at(prog, k));
         if (op.kind == DSR_OP_PUSH) {
             const frame_t f = push(T, op.nbytes);
             if (f.space == SPACE_NONE) { err = DSR_E_NOMEM; break; }
@@ -1309,8 +1379,20 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
                 tr[3 + 3 * npush] = f.size;
             }
             npush++;
-            init_frame(T, f, R.init + op.init_off + (uint64_t)team * op.init_stride, op.init_bytes,
-                       op.nbytes);
+            if (k == 0 && inl && LP.inl_img && f.size <= 16u * 64u) {
+                /* the image (zero-padded to a multiple of 16 bytes) from
+                 * registers, zeros after it */
+                if (16u * T.lane < f.size) {
+                    if (f.space == SPACE_LDS)
+                        *(LDSQ i32x4 *)(dsr_lds + cb_bytes(T.nw) + f.off + 16u * T.lane) = img;
+                    else
+                        *(GLB i32x4 *)(T.stack_hbm + f.off + 16u * T.lane) = img;
+                }
+                wave_sync();
+            } else {
+                init_frame(T, f, R.init + op.init_off + (uint64_t)team * op.init_stride, op.init_bytes,
+                           op.nbytes);
+            }
         } else if (op.kind == DSR_OP_PUBLISH) {
             frame_t f, lf{SPACE_NONE, 0, 0};
             if (VARIANT < DSR_LEAN_BASE && op.body == DSR_BODY_FMA_CHAIN_REFS) {
@@ -1361,7 +1443,9 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
             /* the 1024-thread instance has no registers for a participating
              * master; the host never asks it to (teams above 512 threads) */
             if (VARIANT >= 0 && C.master_joins) {
-                participate<VARIANT>(T, R, C, team, op.body, f, op.loop, inner_pushes);
+                participate<VARIANT>(T, R, C, team, op.body, f, op.loop,
+                                     (inl && LP.inl_loop && op.loop == 0) ? LP.inl_loop0 : R.loops[op.loop],
+                                     inner_pushes);
             } else {
                 end_parallel(T, 0, 0, 0, 0);
             }
@@ -1394,16 +1478,16 @@ __device__ __forceinline__ int32_t run_program(team_t &T, const dsr_dregion &R, 
                     s_off = uniform(lst[1]);
                 }
                 const bool integer_sum = op.body == DSR_BODY_AFFINE_XOR;
-                const i192 sv = s_space == SPACE_LDS
-                                    ? update_sum((LDSQ uint64_t *)(dsr_lds + cb_bytes(T.nw) + s_off), tot, integer_sum,
-                                                 T.lane)
-                                    : update_sum((GLB uint64_t *)(T.stack_hbm + s_off), tot, integer_sum, T.lane);
-                if (T.lane == 0) {
-                    uint64_t *pp = R.partials + ((uint64_t)op.red * R.teams + team) * DSR_PART_WORDS;
-                    store_dev(pp, sv.w0);
-                    store_dev(pp + 1, sv.w1);
-                    store_dev(pp + 2, sv.w2);
-                }
+                /* the team's partial is stored inside each branch: where the
+                 * two would merge the compiler waits for every outstanding
+                 * memory operation of the wave, its loop stores included */
+                uint64_t *pp = RS.partials + ((uint64_t)op.red * RS.teams + team) * DSR_PART_WORDS;
+                if (s_space == SPACE_LDS)
+                    store_partial(pp, update_sum((LDSQ uint64_t *)(dsr_lds + cb_bytes(T.nw) + s_off), tot,
+                                                 integer_sum, T.lane), T.lane);
+                else
+                    store_partial(pp, update_sum((GLB uint64_t *)(T.stack_hbm + s_off), tot, integer_sum, T.lane),
+                                  T.lane);
             }
             wave_sync();
             /* a global reference list dies with its parallel region */
@@ -1450,26 +1534,6 @@ __device__ __forceinline__ i192 sum_partials(const uint64_t *base, uint32_t cnt,
         for (int u = 0; u < 8; ++u) s = add192(s, i192{w[u][0], w[u][1], w[u][2]});
     }
     return wave_sum192(s);
-}
-
-/* The region descriptor fields the arrival and the combine use, held in
- * registers: read once before the arrival atomics, so no fence between
- * them makes the last team reload the descriptor from memory. */
-struct region_sums {
-    uint64_t *partials;
-    dsr_dresult *result;
-    uint32_t teams, n_red, red_kind_mask;
-};
-
-__device__ __forceinline__ region_sums sums_of(const dsr_dregion &R)
-{
-    region_sums S;
-    S.partials = R.partials;
-    S.result = R.result;
-    S.teams = uniform(R.teams);
-    S.n_red = uniform(R.n_red);
-    S.red_kind_mask = uniform(R.red_kind_mask);
-    return S;
 }
 
 /* Last team: the region's reductions from the (group) partials, exact in
@@ -1580,13 +1644,24 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &RD, uint32_t team
  * host memory does not pass the device's earlier write to it).  Every item
  * below the count read here is served; none above it is.  The count is
  * returned to the host, which takes back a request it published too late. */
-__device__ __forceinline__ void close_server(const dsr_dlaunch &LP)
+__device__ __forceinline__ void close_server(const dsr_dlaunch &LP, uint32_t reason, uint32_t it, uint32_t pub,
+                                             uint64_t idle)
 {
     uint32_t *ctr = LP.counter;
     uint32_t open = 0;
     if (!__hip_atomic_compare_exchange_strong(ctr + DSR_SRV_STATE, &open, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT))
         return;
+    /* why, for the host's status: the reason (1 stop, 2 idle), the closing
+     * workgroup, the item it waited for, the published count it saw and
+     * the idle ticks it measured */
+    uint32_t *why = LP.closing + 1;
+    __hip_atomic_store(why, reason, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(why + 1, (uint32_t)blockIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(why + 2, it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(why + 3, pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(why + 4, (uint32_t)idle, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(why + 5, (uint32_t)(idle >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(LP.closing, 1u, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_SYSTEM);
     __atomic_thread_fence(__ATOMIC_SEQ_CST);
     const uint32_t h = __hip_atomic_load(LP.published, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1608,9 +1683,9 @@ __device__ __forceinline__ void close_server(const dsr_dlaunch &LP)
  * makes the request's device-memory inputs visible.
  *
  * Closing is one decision for the whole server, never a workgroup's own:
- * it happens when the host asks to stop, or when the device copy of the
- * published count has not changed for idle_limit ticks (a clock shared by
- * every workgroup).  The server then serves every item published before
+ * it happens when the host asks to stop, or when a waiting workgroup has
+ * seen the device copy of the published count stay unchanged for
+ * idle_limit ticks of its own clock.  The server then serves every item published before
  * the close and no other, so a workgroup leaves only while holding an
  * item nobody will publish to it, and no claimed item is lost.  Nothing
  * here waits for another workgroup, so the server does not rely on its
@@ -1620,11 +1695,19 @@ __device__ __forceinline__ bool wait_item(const dsr_dlaunch &LP, uint32_t it, ui
     uint32_t ok = 0;
     if (lane == 0) {
         uint32_t *ctr = LP.counter;
-        uint64_t *last = (uint64_t *)(ctr + DSR_SRV_LAST);
         uint32_t nap = 0;
+        /* idleness is timed on this wave's own clock from the last change
+         * of the published count it saw: clocks of different workgroups
+         * (other XCDs) are never compared */
+        uint32_t seen = __hip_atomic_load(ctr + DSR_SRV_PUB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t seen_at = (uint64_t)wall_clock64();
         for (;;) {
             const uint32_t pub = __hip_atomic_load(ctr + DSR_SRV_PUB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (it < pub) { ok = 1; break; }
+            if (pub != seen) {
+                seen = pub;
+                seen_at = (uint64_t)wall_clock64();
+            }
             const uint32_t st = __hip_atomic_load(ctr + DSR_SRV_STATE, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
             if (st == 2) {
                 /* closed: items below the final count were made visible
@@ -1637,25 +1720,18 @@ __device__ __forceinline__ bool wait_item(const dsr_dlaunch &LP, uint32_t it, ui
                     const uint32_t h = __hip_atomic_load(LP.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     if (h != pub) {
                         __hip_atomic_fetch_max(ctr + DSR_SRV_PUB, h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(last, wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         ok = 1;
                         break;
                     }
                     if (__hip_atomic_load(LP.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
-                        close_server(LP);
+                        close_server(LP, 1u, it, pub, 0);
                         continue;
                     }
                     nap = 0;
                 }
-                /* another workgroup may store a newer time into `last`
-                 * after this wave read its clock and before its load of
-                 * `last` is served: the difference is then negative, which
-                 * means recent work, not idleness (unsigned, it would wrap
-                 * to a huge value and close a busy server) */
-                const uint64_t t_last = __hip_atomic_load(last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const int64_t idle = (int64_t)((uint64_t)wall_clock64() - t_last);
-                if (idle > (int64_t)LP.idle_limit) {
-                    close_server(LP);
+                const uint64_t idle = (uint64_t)wall_clock64() - seen_at;
+                if (idle > LP.idle_limit) {
+                    close_server(LP, 2u, it, pub, idle);
                     continue;
                 }
             }
@@ -1743,10 +1819,6 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
         const uint64_t now = wall_clock64();
         if (blockIdx.x == 0 && LP.done_ts)
             __hip_atomic_store(LP.done_ts, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        /* the idle clock starts with the first workgroup to run */
-        uint64_t zero = 0;
-        __hip_atomic_compare_exchange_strong((uint64_t *)(LP.counter + DSR_SRV_LAST), &zero, now,
-                                             __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(LP.wg_started + blockIdx.x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     if (LP.start_ts && blockIdx.x == 0 && T.wave == C.nw - 1 && T.lane == 0) *LP.start_ts = wall_clock64();
@@ -1778,8 +1850,9 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
                 }
                 team_reset(T);
             }
-            const dsr_dregion &R = (!lean && C.serve) ? stage_request(T, LP.regions + region) : LP.regions[region];
-            run_program<VARIANT>(T, R, C, region, team, barriers, inner_pushes);
+            const dsr_dregion &R = (!lean && C.serve) ? stage_request(T, LP.regions + region)
+                                                        : ((lean && LP.has_single) ? LP.single : LP.regions[region]);
+            run_program<VARIANT>(T, R, C, LP, single, region, team, barriers, inner_pushes);
             uint32_t *tr = (single && C.trace && R.trace) ? R.trace + (uint64_t)team * DSR_TRACE_WORDS : nullptr;
             if (tr && T.lane == 0) tr[87] = (uint32_t)wall_clock64();
             if (!lean && C.serve) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); /* outputs out of L2 */
@@ -1809,8 +1882,10 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
             barriers++;
             if (!go) break;
             const uint32_t region = uniform(header(T)->region), team = uniform(header(T)->team);
-            participate<VARIANT>(T, (!lean && C.serve) ? *serve_area(T) : LP.regions[region], C, team, body, f, loop,
-                                 inner_pushes);
+            const dsr_dregion &R = (!lean && C.serve) ? *serve_area(T)
+                                                      : ((lean && LP.has_single) ? LP.single : LP.regions[region]);
+            participate<VARIANT>(T, R, C, team, body, f, loop,
+                                 (lean && LP.inl_loop && loop == 0) ? LP.inl_loop0 : R.loops[loop], inner_pushes);
             barriers++;
         }
     }

@@ -58,7 +58,8 @@ EXPORTS = ("dsr_init", "dsr_destroy", "dsr_region_begin", "dsr_push", "dsr_publi
            "dsr_serve_start", "dsr_serve_submit", "dsr_serve_poll", "dsr_serve_pending",
            "dsr_serve_replay", "dsr_serve_stop", "dsr_occupancy_model", "dsr_region_occupancy",
            "dsr_publish_list", "dsr_control_bytes", "dsr_serve_status", "dsr_launch_static",
-           "dsr_static_bytes", "dsr_stream_ceiling")
+           "dsr_static_bytes", "dsr_stream_ceiling", "dsr_autotune_plan",
+           "dsr_serve_class_for")
 
 
 class dsr_ref(C.Structure):
@@ -77,7 +78,7 @@ class dsr_loop(C.Structure):
                 ("out", C.c_void_p), ("ni", C.c_uint32), ("nf", C.c_uint32),
                 ("alen", C.c_uint32), ("arrays", C.c_uint32), ("len", C.c_uint32),
                 ("schedule", C.c_uint32), ("tail_pct", C.c_uint32), ("block", C.c_uint32),
-                ("depth", C.c_uint32), ("pad", C.c_uint32)]
+                ("depth", C.c_uint32), ("deref", C.c_uint32)]
 
 
 class dsr_tune(C.Structure):
@@ -92,13 +93,14 @@ class dsr_tune(C.Structure):
 class dsr_serve_cfg(C.Structure):
     _fields_ = [("tune", dsr_tune), ("slots", C.c_uint32), ("slot_bytes", C.c_uint32),
                 ("max_teams", C.c_uint32), ("ring_items", C.c_uint32), ("idle_ms", C.c_uint32),
-                ("budget_pct", C.c_uint32)]
+                ("budget_pct", C.c_uint32), ("n_classes", C.c_uint32), ("class_slab", C.c_uint32 * 4),
+                ("class_grid", C.c_uint32 * 4)]
 
 
 class dsr_done(C.Structure):
     _fields_ = [("ticket", C.c_uint64), ("status", C.c_int32), ("n_red", C.c_int32),
                 ("f64", C.c_double * 8), ("i64", C.c_int64 * 8), ("fixed", (C.c_uint64 * 3) * 8),
-                ("device_us", C.c_double)]
+                ("device_us", C.c_double), ("lds_class", C.c_int32), ("pad", C.c_int32)]
 
     def as_dict(self):
         fx = []
@@ -106,7 +108,8 @@ class dsr_done(C.Structure):
             w = self.fixed[i]
             fx.append(_fixed([w[0], w[1], w[2]]))
         return {"ticket": self.ticket, "status": self.status, "f64": list(self.f64[:self.n_red]),
-                "i64": list(self.i64[:self.n_red]), "fixed": fx, "device_us": self.device_us}
+                "i64": list(self.i64[:self.n_red]), "fixed": fx, "device_us": self.device_us,
+                "lds_class": self.lds_class}
 
 
 class dsr_result_rec(C.Structure):
@@ -126,10 +129,12 @@ RESULT_REC_BYTES = C.sizeof(dsr_result_rec)
 class dsr_serve_stat(C.Structure):
     _fields_ = [("grid", C.c_uint32), ("started", C.c_uint32), ("exited", C.c_uint32),
                 ("closed", C.c_uint32), ("final_items", C.c_uint32), ("published", C.c_uint32),
-                ("in_flight", C.c_uint32), ("pad", C.c_uint32)]
+                ("in_flight", C.c_uint32), ("classes", C.c_uint32), ("close_reason", C.c_uint32),
+                ("close_block", C.c_uint32), ("close_item", C.c_uint32), ("close_seen", C.c_uint32),
+                ("close_idle_us", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class dsr_hw_model(C.Structure):
@@ -188,6 +193,8 @@ def lib():
             "dsr_pop": [P, i32],
             "dsr_launch": [P, P],
             "dsr_launch_static": [P, P, P],
+            "dsr_autotune_plan": [P, C.POINTER(dsr_tune), i32, C.POINTER(i32)],
+            "dsr_serve_class_for": [C.POINTER(u32), i32, P],
             "dsr_stream_ceiling": [P, P, C.c_uint64, u32, u32, P],
             "dsr_region_sync": [P],
             "dsr_region_reduction": [P, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
@@ -288,11 +295,12 @@ def dsr_publish(region, frame, body, n, inp=0, out=0, chunk=0, ni=0, nf=0, alen=
 
 
 def dsr_publish_list(region, refs, body, n, inp=0, out=0, chunk=0, ni=0, nf=0, alen=0,
-                     schedule=0, tail_pct=0, block=0):
+                     schedule=0, tail_pct=0, block=0, deref=0):
     """refs: (frame, byte offset) per variable: the exact sum slot, the ni
-    int32 scalars, the nf fp64 scalars, then the array if alen > 0."""
+    int32 scalars, the nf fp64 scalars, then the array if alen > 0.
+    deref=1: the loop reads every scalar through its reference on each batch."""
     arr = (dsr_ref * max(1, len(refs)))(*[dsr_ref(int(f), int(o)) for f, o in refs])
-    L = dsr_loop(n, chunk, inp or None, out or None, ni, nf, alen, 0, 0, schedule, tail_pct, block)
+    L = dsr_loop(n, chunk, inp or None, out or None, ni, nf, alen, 0, 0, schedule, tail_pct, block, 0, deref)
     return _check(lib().dsr_publish_list(region, arr, len(refs), body, C.byref(L)), "dsr_publish_list")
 
 
@@ -454,6 +462,14 @@ def dsr_batch_free(batch):
     return _check(lib().dsr_batch_free(batch), "dsr_batch_free")
 
 
+def dsr_autotune_plan(batch, max_n=64):
+    """Model-seeded autotuner candidates (list of dicts)."""
+    buf = (dsr_tune * max_n)()
+    n = C.c_int32()
+    _check(lib().dsr_autotune_plan(batch, buf, max_n, C.byref(n)), "dsr_autotune_plan")
+    return [buf[k].as_dict() for k in range(min(n.value, max_n))]
+
+
 def dsr_autotune(batch, candidates, reps=3, stream=0):
     """candidates: list of dicts of dsr_tune fields.  Returns (best dict,
     list of mean ms per candidate, negative when skipped)."""
@@ -483,12 +499,26 @@ def dsr_batch_replay_serial(batch, prog, arrival_s):
 # ---- served form ------------------------------------------------------------
 def dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=65536, overflow_threshold=0, master_joins=0,
                     grid=0, slots=256, slot_bytes=40960, max_teams=64, ring_items=1 << 16,
-                    idle_ms=10000, budget_pct=0):
+                    idle_ms=10000, budget_pct=0, classes=None):
+    """classes: list of (LDS slab bytes, grid or 0) per LDS class, or None."""
+    cls = list(classes or [])
+    slabs = (C.c_uint32 * 4)(*[c[0] for c in cls])
+    grids = (C.c_uint32 * 4)(*[c[1] for c in cls])
     cfg = dsr_serve_cfg(dsr_tune(wg_size, lds_slab_bytes, overflow_threshold, master_joins, grid, 0),
-                        slots, slot_bytes, max_teams, ring_items, idle_ms, budget_pct)
+                        slots, slot_bytes, max_teams, ring_items, idle_ms, budget_pct, len(cls), slabs, grids)
     srv = C.c_void_p()
     _check(lib().dsr_serve_start(ctx, C.byref(cfg), C.byref(srv)), "dsr_serve_start")
     return srv
+
+
+def dsr_serve_class_for(slabs, region):
+    """Index of the LDS class (of on-chip stack sizes `slabs`) the request
+    with this program is admitted to."""
+    arr = (C.c_uint32 * len(slabs))(*slabs)
+    rc = lib().dsr_serve_class_for(arr, len(slabs), region)
+    if rc < 0:
+        raise DsrError(rc, "dsr_serve_class_for")
+    return rc
 
 
 def dsr_serve_submit(server, region, outs=None):

@@ -272,3 +272,22 @@ def test_static_launch_host_checks():
     D.dsr_region_free(r)
     D.dsr_region_free(r2)
     D.dsr_destroy(ctx)
+
+
+def test_deref_only_for_scalar_lists():
+    """Per-batch reads through the list (deref) exist for the list publish of
+    scalars only: a frame publish or a list with an array is refused."""
+    ctx = host_ctx(wg_size=256, lds_slab_bytes=4096, hbm_slab_bytes=4096, max_teams=8)
+    r = D.dsr_region_begin(ctx, 2)
+    f = D.dsr_push(r, 48, b"")
+    L = D.dsr_loop(100, 0, 16, 16, 2, 1, 0, 0, 0, 0, 0, 0, 0, 1)
+    assert D.lib().dsr_publish(r, f, D.DSR_BODY_FMA_CHAIN, D.C.byref(L)) == D.DSR_E_INVAL
+    refs = [(f, 0), (f, 32), (f, 36), (f, 24)]
+    D.dsr_publish_list(r, refs, D.DSR_BODY_FMA_CHAIN_REFS, 100, inp=16, out=16, ni=2, nf=1, deref=1)
+    g = D.dsr_push(r, 64, b"")
+    with pytest.raises(D.DsrError) as e:
+        D.dsr_publish_list(r, [(g, 0), (g, 32), (g, 36), (g, 24), (g, 48)], D.DSR_BODY_FMA_CHAIN_REFS, 100,
+                           inp=16, out=16, ni=2, nf=1, alen=3, deref=1)
+    assert e.value.code == D.DSR_E_INVAL
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)

@@ -215,3 +215,33 @@ def test_list_regions_in_a_batch():
     for r in regs:
         D.dsr_region_free(r)
     D.dsr_destroy(ctx)
+
+
+@pytest.mark.parametrize("ni,nf,lds,flags", [
+    (4, 4, 4096, 0),                       # on-chip list, frame in LDS
+    (10, 9, 4096, D.DSR_F_GLOBAL_LISTS),   # global list, frame in LDS
+    (32, 32, 4096, 0),                     # 65 references: a global list
+    (3, 5, 0, 0),                          # frame in HBM, on-chip list
+])
+def test_list_read_every_batch(ni, nf, lds, flags):
+    """deref=1: every batch reads each scalar through its reference again;
+    the results are those of the hoisted reads and of the oracle."""
+    n = (1 << 17) + 77
+    say("list deref", ni, nf, lds, flags)
+    s_i, s_f, _, x_np = chain_inputs(ni, nf, 0, n, seed=23)
+    size, refs = one_frame_refs(ni, nf, 0)
+    init = S.fma_chain_init(s_i, s_f, None)
+    ctx = D.dsr_init(wg_size=256, lds_slab_bytes=lds, hbm_slab_bytes=8192, max_teams=64, flags=flags)
+    x = torch.from_numpy(x_np).cuda()
+    for deref in (1, 0):
+        y = torch.full((n,), -3.0, dtype=torch.float64, device="cuda")
+        r = D.dsr_region_begin(ctx, 7)
+        f = D.dsr_push(r, size, init)
+        D.dsr_publish_list(r, refs, D.DSR_BODY_FMA_CHAIN_REFS, n, inp=x.data_ptr(), out=y.data_ptr(),
+                           ni=ni, nf=nf, deref=deref)
+        D.dsr_pop(r, f)
+        D.dsr_launch(r, stream())
+        assert D.dsr_region_sync(r) == 0
+        check(r, x_np, s_i, s_f, y)
+        D.dsr_region_free(r)
+    D.dsr_destroy(ctx)

@@ -83,7 +83,11 @@ def wait_started(srv, timeout=2.0):
 def run_one(srv, region, outs=None):
     """Submit one request and wait for it; returns (done, seconds)."""
     t0 = time.perf_counter()
-    D.dsr_serve_submit(srv, region, outs)
+    try:
+        D.dsr_serve_submit(srv, region, outs)
+    except D.DsrError as e:
+        # a refused submit names the server's state (and why it closed)
+        raise AssertionError((str(e), D.dsr_serve_status(srv)))
     got = []
     while not got:
         got = D.dsr_serve_poll(srv)
@@ -110,20 +114,56 @@ def test_serve_output_visible_at_completion(setup):
     its completion is polled, while the server keeps running."""
     ctx, insts, xs, ys, regs = setup
     say("serve visibility")
+    # every output buffer exists before the server starts: an allocation
+    # that synchronises the device waits for the resident kernel
+    outs = [torch.zeros_like(ys[k]) for k in range(12)]
+    torch.cuda.current_stream().synchronize()
     srv = D.dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=32768, slots=16, slot_bytes=40960,
                             max_teams=64, idle_ms=20000)
     try:
         wait_started(srv)
         for k in range(12):
             ins, x, yr, rs, fx = insts[k]
-            out = torch.zeros_like(ys[k])
-            torch.cuda.current_stream().synchronize()
+            out = outs[k]
             d, secs = run_one(srv, regs[k], [out.data_ptr()])
             assert d["status"] == 0 and d["f64"] == [rs]
             assert secs < REQUEST_BOUND_S, (k, secs)
             assert np.array_equal(out.cpu().numpy().view(np.uint64), yr.view(np.uint64)), k
     finally:
         D.dsr_serve_stop(srv)
+
+
+def test_serve_leaves_room_for_copies(setup):
+    """The default grid leaves workgroup slots free, so the runtime's copy
+    and fill kernels, issued on other streams while the server is resident,
+    run at once instead of waiting for the server to close."""
+    ctx, insts, xs, ys, regs = setup
+    say("serve room for copies")
+    side = torch.cuda.Stream()
+    host = torch.zeros(ys[0].shape, dtype=torch.float64, pin_memory=True)
+    dev = torch.zeros(1 << 20, device="cuda")
+    torch.cuda.synchronize()
+    srv = D.dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=32768, slots=16, slot_bytes=40960,
+                            max_teams=64, idle_ms=20000)
+    try:
+        wait_started(srv)
+        d, _ = run_one(srv, regs[0], [ys[0].data_ptr()])
+        assert d["status"] == 0
+        waits = []
+        for name, work in (("device-to-host copy", lambda: host.copy_(ys[0], non_blocking=True)),
+                           ("fill", lambda: dev.fill_(2.0))):
+            with torch.cuda.stream(side):
+                work()
+            t0 = time.perf_counter()
+            while not side.query() and time.perf_counter() - t0 < 2.0:
+                time.sleep(0.001)
+            waits.append((name, side.query(), time.perf_counter() - t0))
+        st = D.dsr_serve_status(srv)
+        assert all(done for _, done, _ in waits) and not st["closed"], (waits, st)
+        assert np.array_equal(host.numpy(), ys[0].cpu().numpy())
+    finally:
+        D.dsr_serve_stop(srv)
+    torch.cuda.synchronize()
 
 
 def test_serve_light_load_and_idle_close(setup):
@@ -183,15 +223,15 @@ def test_serve_stop_runs_published_requests(setup):
 def test_serve_requests_match_oracle(setup):
     ctx, insts, xs, ys, regs = setup
     say("serve basic")
+    # every instance twice, the second copy into a separate output buffer:
+    # both copies run concurrently in the mix.  The buffers exist before the
+    # server starts (an allocation that synchronises the device waits for
+    # the resident kernel)
+    extra = [torch.zeros_like(y) for y in ys]
+    torch.cuda.current_stream().synchronize()
     srv = D.dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=32768, slots=64, slot_bytes=40960,
                             max_teams=64, idle_ms=20000)
     try:
-        # every instance twice, the second copy into a separate output buffer:
-        # both copies run concurrently in the mix
-        extra = [torch.zeros_like(y) for y in ys]
-        # the server runs on its own stream: buffers must be ready at submit
-        # (a device-wide synchronize would wait for the resident server)
-        torch.cuda.current_stream().synchronize()
         tickets = {}
         done = []
         for k, r in enumerate(regs):
@@ -270,3 +310,38 @@ def test_serve_replay_and_serial(setup):
         if k in set(prog.tolist()):
             assert D.dsr_batch_result(b, k)[1] == rs
     D.dsr_batch_free(b)
+
+
+def test_serve_lds_classes(setup):
+    """Two LDS classes (4 KiB and 40 KiB of on-chip stack per team): every
+    request runs in the class sized to its frames unless that class is full,
+    and its outputs and exact sum equal the oracle's in the mix."""
+    ctx, insts, xs, ys, regs = setup
+    say("serve lds classes")
+    slabs = [4096, 40960]
+    outs = {k: torch.zeros_like(ys[k]) for k in range(24)}
+    torch.cuda.current_stream().synchronize()
+    srv = D.dsr_serve_start(ctx, wg_size=256, slots=16, slot_bytes=40960, max_teams=64, idle_ms=20000,
+                            classes=[(slabs[0], 0), (slabs[1], 0)])
+    want_cls, got = {}, []
+    try:
+        st = wait_started(srv)
+        assert st["classes"] == 2
+        tickets = {}
+        for k in range(24):
+            tickets[submit_retry(srv, regs[k], [outs[k].data_ptr()], sink=got)] = k
+            want_cls[k] = D.dsr_serve_class_for(slabs, regs[k])
+        got += drain(srv, 24 - len(got))
+    finally:
+        D.dsr_serve_stop(srv)
+    seen = set()
+    for d in got:
+        k = tickets[d["ticket"]]
+        ins, x, yr, rs, fx = insts[k]
+        assert d["status"] == 0 and d["f64"] == [rs] and d["fixed"] == [fx], k
+        assert np.array_equal(outs[k].cpu().numpy().view(np.uint64), yr.view(np.uint64)), k
+        # a request runs in its own class, or a larger one while that is full
+        assert slabs[d["lds_class"]] >= slabs[want_cls[k]], (k, d["lds_class"], want_cls[k])
+        seen.add(d["lds_class"])
+    assert sorted(tickets.values()) == list(range(24))
+    assert set(want_cls.values()) == {0, 1}      # the instances need both classes
