@@ -588,14 +588,18 @@ def run_batched(torch, np, D, W, stream, n_inst=10000, seed=3, sample=64):
 
 
 # ---- served ----------------------------------------------------------------------
-def run_served(torch, np, D, W, stream, rates, seconds, pool=1000, seed=4, slots=256, check=192):
+def run_served(torch, np, D, W, stream, rates, seconds, pool=1000, seed=4, slots=256, check=192,
+               serial_seconds=10.0):
     """Poisson arrivals at each rate for `seconds`.  Request q runs instance
     prog[q] drawn uniformly (seeded) from a pool of `pool` instances of the
     seed-4 table (sizes log-uniform as in the batched workload), writing its
     y into a recycled slot buffer.  Every request's exact sum is checked
     against the oracle's.  Then `check` requests drawn from the pool are
     submitted back to back, each with its own output buffer, so that they
-    overlap on the device, and every element of their y is checked."""
+    overlap on the device, and every element of their y is checked.  The
+    comparison form (one launch and synchronisation per request) replays
+    the first `serial_seconds` of each schedule: where it cannot keep up
+    its backlog only grows, and a longer replay would only take longer."""
     from oracle import ref as R
     dev = torch.device("cuda:0")
     Ls, Fs, offs = instance_pool(W, pool, seed)
@@ -634,10 +638,15 @@ def run_served(torch, np, D, W, stream, rates, seconds, pool=1000, seed=4, slots
         served = {"requests": int(len(arr)), "p50_us": pct(lat, 50), "p99_us": pct(lat, 99),
                   "instances_per_s": len(arr) / max(fin, span), "sums_checked": int(len(arr)),
                   "sums_wrong": int(bad)}
-        lat2 = D.dsr_batch_replay_serial(b, prog, arr)
-        fin2 = float((arr + lat2 * 1e-6).max()) if len(arr) else 0.0
-        serial = {"p50_us": pct(lat2, 50), "p99_us": pct(lat2, 99),
-                  "instances_per_s": len(arr) / max(fin2, span)}
+        say("served", rate, served)
+        cut = arr < serial_seconds
+        arr2, prog2 = arr[cut], prog[cut]
+        span2 = max(float(arr2[-1]), 1e-9) if len(arr2) else 1e-9
+        lat2 = D.dsr_batch_replay_serial(b, prog2, arr2)
+        fin2 = float((arr2 + lat2 * 1e-6).max()) if len(arr2) else 0.0
+        serial = {"seconds": float(min(seconds, serial_seconds)), "requests": int(len(arr2)),
+                  "p50_us": pct(lat2, 50), "p99_us": pct(lat2, 99),
+                  "instances_per_s": len(arr2) / max(fin2, span2)}
         res["%dk_per_s" % (rate // 1000)] = {"served": served, "serial_launch_sync": serial}
         say("served", rate, served, serial)
     # outputs in the mix: requests submitted back to back, each with its own y
@@ -756,6 +765,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of each served arrival schedule (the full workload is 60)")
     ap.add_argument("--serve-rates", default="1000,10000,50000")
+    ap.add_argument("--serve-serial-seconds", type=float, default=10.0,
+                    help="schedule seconds the launch-per-request comparison replays")
     ap.add_argument("--arrays-shapes", default="",
                     help="comma list of AxLEN array shapes for the arrays part (default: all 16)")
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_CMD", "WRITE_CMD"),
@@ -845,7 +856,8 @@ def main():
     if "served" in parts:
         say("served")
         rates = [int(v) for v in args.serve_rates.split(",") if v]
-        out["served"] = run_served(torch, np, D, W, stream, rates, args.serve_seconds)
+        out["served"] = run_served(torch, np, D, W, stream, rates, args.serve_seconds,
+                                   serial_seconds=args.serve_serial_seconds)
     if "cpu" in parts:
         say("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(W)
