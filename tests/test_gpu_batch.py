@@ -138,3 +138,58 @@ def test_autotune_picks_a_valid_candidate():
     check_all(b, insts, offs, x_np, y_d, "tuned")
     D.dsr_batch_free(b)
     D.dsr_destroy(ctx)
+
+
+def test_cfg4_full_batch_sampled():
+    """The batched workload at its full size: 10,000 regions with loop
+    lengths log-uniform on [256, 2^20] and frames on [8, 32768] bytes (about
+    1.3e9 elements) in one persistent launch.  Every region must report
+    success; the 8 longest regions, the 8 with the largest frames and 32
+    drawn at random are checked against the oracle element by element and
+    by their exact sums."""
+    say("cfg4 full batch")
+    n_inst, seed, chunk = 10000, 3, 65536
+    Ls, Fs = W.cfg4_descriptors(n_inst, seed=seed)
+    offs = np.zeros(n_inst + 1, np.int64)
+    offs[1:] = np.cumsum((Ls + 63) // 64 * 64)
+    x_d = torch.empty(int(offs[-1]), dtype=torch.float32, device="cuda")
+    r = 0
+    while r < n_inst:                       # host pieces of ~256 MB
+        r1 = r
+        while r1 < n_inst and offs[r1] - offs[r] < (1 << 26):
+            r1 += 1
+        host = np.empty(int(offs[r1] - offs[r]), np.float32)
+        for q in range(r, r1):
+            a = int(offs[q] - offs[r])
+            host[a:a + int(Ls[q])] = W.instance_x(q, int(Ls[q]), seed=seed)
+        x_d[int(offs[r]):int(offs[r1])].copy_(torch.from_numpy(host))
+        r = r1
+    y_d = torch.zeros(int(offs[-1]), dtype=torch.float64, device="cuda")
+    ctx = D.dsr_init(wg_size=256, lds_slab_bytes=65536, hbm_slab_bytes=65536, max_teams=4096)
+    insts = [W.cfg4_instance(q, int(Ls[q]), int(Fs[q]), seed=seed) for q in range(n_inst)]
+    regions = [D.fma_chain_region(ctx, max(1, -(-int(Ls[q]) // chunk)), ins.s_i32, ins.s_f64, ins.arr,
+                                  int(Ls[q]), x_d.data_ptr() + 4 * int(offs[q]),
+                                  y_d.data_ptr() + 8 * int(offs[q])) for q, ins in enumerate(insts)]
+    b = D.dsr_batch_create(ctx, regions)
+    for reg in regions:
+        D.dsr_region_free(reg)
+    D.dsr_batch_launch(b, stream())
+    assert D.dsr_batch_sync(b) == 0
+    statuses = [D.dsr_batch_result(b, q)[3] for q in range(n_inst)]
+    assert all(st == 0 for st in statuses)
+    rng = np.random.default_rng(11)
+    pick = sorted(set(np.argsort(Ls)[-8:].tolist()) | set(np.argsort(Fs)[-8:].tolist())
+                  | set(rng.choice(n_inst, 32, replace=False).tolist()))
+    x_np = None
+    for q in pick:
+        ins = insts[q]
+        lo, hi = int(offs[q]), int(offs[q]) + ins.L
+        x_np = x_d[lo:hi].cpu().numpy()
+        yr = R.fma_chain(x_np, ins.s_i32, ins.s_f64, ins.arr)
+        assert np.array_equal(y_d[lo:hi].cpu().numpy().view(np.uint64), yr.view(np.uint64)), q
+        _, f64, fixed, st = D.dsr_batch_result(b, int(q))
+        assert st == 0 and fixed == R.fixed75_sum(yr) and f64 == R.exact_sum(yr), q
+    D.dsr_batch_free(b)
+    D.dsr_destroy(ctx)
+    del x_d, y_d
+    torch.cuda.empty_cache()

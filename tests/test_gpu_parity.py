@@ -450,6 +450,34 @@ def test_cfg3_gather(A, length, hbm_only, nested):
     D.dsr_destroy(ctx)
 
 
+@pytest.mark.parametrize("A,length,hbm_only", [(2, 4096, 0), (2, 4096, 1), (3, 16384, 0)])
+def test_cfg3_full_size(A, length, hbm_only):
+    """The nested gather at its full size and launch shape (2^26 outputs,
+    2048 teams of 256 threads, the stack sized as the bench sizes it): a
+    32 KiB frame on chip or on the HBM-only stack, and a 192 KiB frame that
+    only the HBM slot holds; every output element against the oracle."""
+    say("cfg3 full A", A, "len", length, "hbm_only", hbm_only)
+    arrs = W.cfg3_arrays(A, length)
+    n, teams = 1 << 26, 2048
+    frame = 4 * A * length
+    slab = 0 if (hbm_only or frame > LDS_MAX4) else (frame + 15) // 16 * 16
+    ctx = D.dsr_init(wg_size=256, lds_slab_bytes=slab, hbm_slab_bytes=(frame + 15) // 16 * 16,
+                     max_teams=teams, master_joins=1)
+    out = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+
+    def build(r):
+        f = D.dsr_push(r, frame, D.gather_frame(arrs))
+        D.dsr_publish(r, f, D.DSR_BODY_GATHER_NESTED, n, out=out.data_ptr(), arrays=A, length=length)
+        D.dsr_pop(r, f)
+    st, r = run_region(ctx, teams, build)
+    assert st == 0
+    assert np.array_equal(out.cpu().numpy(), R.gather(arrs, 0, n))
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+    del out
+    torch.cuda.empty_cache()
+
+
 def test_two_frames_spill_and_lifo():
     """Two frames: the first fills the LDS stack, the second spills; a
     gather over each; pops in LIFO order.  Placement matches the simulator."""
