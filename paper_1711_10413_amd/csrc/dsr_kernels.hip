@@ -161,20 +161,41 @@ __device__ __forceinline__ i192 widen(const lane_acc &a)
     return add192(add192(a.big, bins_fixed(a)), from_i64(a.i));
 }
 
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m)
+/* One DPP step of the wave sum: every 32-bit part of v moved from the lane
+ * the control selects (zero where that lane is outside the row, and in the
+ * rows the mask leaves out), then added with carries. */
+template <int CTRL, int ROWS>
+__device__ __forceinline__ i192 dpp_add192(i192 v)
 {
-    return (uint64_t)__shfl_xor((unsigned long long)v, m, 64);
+    const uint32_t p[6] = {(uint32_t)v.w0, (uint32_t)(v.w0 >> 32), (uint32_t)v.w1,
+                           (uint32_t)(v.w1 >> 32), (uint32_t)v.w2, (uint32_t)(v.w2 >> 32)};
+    uint32_t q[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) q[k] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)p[k], CTRL, ROWS, 0xf, true);
+    return add192(v, i192{q[0] | ((uint64_t)q[1] << 32), q[2] | ((uint64_t)q[3] << 32), q[4] | ((uint64_t)q[5] << 32)});
 }
 
-/* Sum over the 64 lanes of a wave (every lane gets the total). */
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+/* Sum over the 64 lanes of a wave, returned to every lane: a running sum
+ * inside each row of 16 lanes (row shifts by 1, 2, 4 and 8), then the row
+ * totals carried across rows (lane 15 into row 1 and 3, lane 31 into rows 2
+ * and 3), so lane 63 holds the total; all in VALU moves, no LDS round
+ * trips.  Every lane of the wave takes part. */
 __device__ __forceinline__ i192 wave_sum192(i192 v)
 {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        i192 o{shfl_xor64(v.w0, m), shfl_xor64(v.w1, m), shfl_xor64(v.w2, m)};
-        v = add192(v, o);
-    }
-    return v;
+    v = dpp_add192<0x111, 0xf>(v);   /* row_shr:1 */
+    v = dpp_add192<0x112, 0xf>(v);   /* row_shr:2 */
+    v = dpp_add192<0x114, 0xf>(v);   /* row_shr:4 */
+    v = dpp_add192<0x118, 0xf>(v);   /* row_shr:8 */
+    v = dpp_add192<0x142, 0xa>(v);   /* row_bcast:15 into rows 1 and 3 */
+    v = dpp_add192<0x143, 0xc>(v);   /* row_bcast:31 into rows 2 and 3 */
+    return i192{readlane64(v.w0, 63), readlane64(v.w1, 63), readlane64(v.w2, 63)};
 }
 
 __device__ __forceinline__ uint64_t bits64(uint64_t w0, uint64_t w1, uint64_t w2, int p)
