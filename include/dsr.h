@@ -137,7 +137,8 @@ typedef struct dsr_config {
 /* One published parallel loop.  Pointers are device pointers. */
 typedef struct dsr_loop {
     uint64_t n;        /* iterations of the worksharing loop                   */
-    uint64_t chunk;    /* iterations per team (0: ceil(n/teams) rounded up to 64);
+    uint64_t chunk;    /* iterations per team (0: ceil(n/teams) rounded up to 64,
+                          or to 1024 when that is at least 16384);
                           team t runs [t*chunk, min(n, (t+1)*chunk))            */
     const void *in;    /* FMA_CHAIN: float x[n]                                */
     void *out;         /* int32 out[n] or double y[n]                           */
