@@ -2,8 +2,9 @@
 
 Headline workload (one step): the scalar-sharing sweep.  For each K in
 {1, 2, 4, 8, 16, 32, 64} one region of 512 teams x 256 threads (one master
-wave, three worker waves): the master shares K scalars (ceil(K/2) int32,
-floor(K/2) fp64) through its LDS team stack, the workers run
+wave, three worker waves; by default the master joins the loop once it has
+published): the master shares K scalars (ceil(K/2) int32, floor(K/2) fp64)
+through its LDS team stack, the participating waves run
 y[i] = fma chain over x[i] for 2**24 fp32 elements and reduce exactly into
 the shared slot.  `value` is region instances per second over the timed
 steps.  Inputs are seeded synthetic data resident in HBM before timing;
@@ -22,7 +23,10 @@ The same JSON line also reports the other workloads of the method:
   served     Poisson arrivals at 1k, 10k, 50k requests/s: p50/p99 latency
              and instances/s, resident server vs one launch + sync per
              request
-and the CPU oracle timed on a bounded sample (one thread).
+  ceiling    a plain streaming kernel with the sweep's read/write mix at the
+             sweep's launch shape and at a full grid
+  lists      the sweep's chain published through reference lists (section 5.2)
+and the CPU oracle (one core and all cores, medians of five runs).
 """
 import argparse
 import json
