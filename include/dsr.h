@@ -441,8 +441,9 @@ int dsr_autotune_plan(dsr_batch *b, dsr_tune *out, int32_t max, int32_t *n_out);
  * completion record that the host polls.
  *
  * Admission: a request is rejected with DSR_E_NOMEM if one of its teams'
- * frames fits neither the LDS stack nor the HBM slot of a server team (the
- * same rule the device applies), and deferred with DSR_E_BUSY while no slot
+ * frames fits neither the LDS stack of any class nor the HBM slot of a
+ * server team (the same rule the device applies), and deferred with
+ * DSR_E_BUSY while no slot
  * is free or while the LDS or HBM bytes of the admitted, unfinished
  * requests' team stacks would exceed the server's budget (the resident
  * teams' LDS slabs and HBM slots).  Budgets are returned on completion.

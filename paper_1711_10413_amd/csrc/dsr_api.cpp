@@ -1569,14 +1569,17 @@ extern "C" int dsr_serve_submit(dsr_server *S, dsr_region *r, void *const *outs,
     for (int32_t k = 0; k < n_cls; ++k)
         if (std::find(order.begin(), order.end(), k) == order.end()) order.push_back(k);
     int32_t kc = -1;
-    bool busy = false;
+    bool busy = false, placeable = false;
     uint64_t lcost = 0, hcost = 0;
     const uint32_t thr = S->tune.overflow_threshold ? S->tune.overflow_threshold : 0xFFFFFFFFu;
     for (int32_t k : order) {
         serve_class &K = S->cls[k];
-        if (__atomic_load_n(K.closing, __ATOMIC_SEQ_CST) != 0) continue;
         uint64_t lp = 0, hp = 0;
-        if (!stack_peaks(r, K.slab, thr, S->ctx->cfg.hbm_slab_bytes, &lp, &hp)) return DSR_E_NOMEM;
+        /* a class whose stacks cannot hold one of the request's frames is
+         * passed over; NOMEM only when no class can */
+        if (!stack_peaks(r, K.slab, thr, S->ctx->cfg.hbm_slab_bytes, &lp, &hp)) continue;
+        placeable = true;
+        if (__atomic_load_n(K.closing, __ATOMIC_SEQ_CST) != 0) continue;
         const uint64_t lc = lp * r->teams, hc = hp * r->teams;
         /* ring space: items of the oldest unfinished request bound the writer */
         uint32_t floor_item = K.pub;
@@ -1595,7 +1598,7 @@ extern "C" int dsr_serve_submit(dsr_server *S, dsr_region *r, void *const *outs,
         hcost = hc;
         break;
     }
-    if (kc < 0) return busy ? DSR_E_BUSY : DSR_E_STATE;
+    if (kc < 0) return !placeable ? DSR_E_NOMEM : (busy ? DSR_E_BUSY : DSR_E_STATE);
     if (S->free_slots.empty()) return DSR_E_BUSY;
     serve_class &K = S->cls[kc];
 
