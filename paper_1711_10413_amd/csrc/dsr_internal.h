@@ -5,6 +5,7 @@
 #ifndef DSR_INTERNAL_H
 #define DSR_INTERNAL_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #define DSR_MAX_RED 8
@@ -43,20 +44,23 @@ struct dsr_dloop {
     uint32_t pad;
 };
 
-/* Per-launch result block (device memory, written by the last team). */
+/* Per-launch result block (device memory, written by the last team).  The
+ * fields the host reads come first: it copies only DSR_RESULT_HOST_BYTES. */
 struct dsr_dresult {
     int32_t error;         /* accumulating: first team error of this launch */
     uint32_t arrived;      /* teams that finished; reset by the last team   */
     int32_t final_error;   /* the launch's error, written by the last team  */
     uint32_t done;         /* launch counter, bumped by the last team       */
+    uint64_t fixed[DSR_MAX_RED][3];
+    double f64[DSR_MAX_RED];
+    int64_t i64[DSR_MAX_RED];
+    /* device-side counters from here on */
     uint32_t claim[DSR_MAX_LOOPS]; /* dynamic-tail block counters; reset by the last team */
     /* arrival tree: teams count into DSR_ARRIVE_GROUPS group counters (64 B
      * apart), the last team of each group into `arrived` */
     uint32_t group[DSR_ARRIVE_GROUPS * 16];
-    uint64_t fixed[DSR_MAX_RED][3];
-    double f64[DSR_MAX_RED];
-    int64_t i64[DSR_MAX_RED];
 };
+#define DSR_RESULT_HOST_BYTES offsetof(dsr_dresult, claim)
 
 /* Everything one region needs on the device. */
 struct dsr_dregion {
