@@ -504,6 +504,7 @@ static int upload(dsr_region *r)
     R.n_red = r->n_red;
     R.red_kind_mask = r->red_kind_mask;
     R.n_loops = (uint32_t)r->loops.size();
+    R.init_size = (uint32_t)r->init.size();
     if (hipMalloc((void **)&r->d_self, sizeof(dsr_dregion)) != hipSuccess) return DSR_E_NOMEM;
     if ((rc = hip_ok(hipMemcpy(r->d_self, &R, sizeof(R), hipMemcpyHostToDevice)))) return rc;
     r->desc = R;
@@ -745,6 +746,7 @@ extern "C" int dsr_launch_static(dsr_region *r, dsr_result_rec *result, void *st
     R.n_red = r->n_red;
     R.red_kind_mask = r->red_kind_mask;
     R.n_loops = (uint32_t)r->loops.size();
+    R.init_size = (uint32_t)r->init.size();
     if (hipMemcpyAsync(ws + L.desc, &R, sizeof(R), hipMemcpyHostToDevice, s) != hipSuccess) return DSR_E_HIP;
     if (!r->ops.empty() &&
         hipMemcpyAsync(ws + L.ops, r->ops.data(), r->ops.size() * sizeof(dsr_op), hipMemcpyHostToDevice, s) !=
@@ -904,6 +906,7 @@ extern "C" int dsr_batch_create(dsr_ctx *ctx, dsr_region *const *regions, int32_
         R.n_red = r->n_red;
         R.red_kind_mask = r->red_kind_mask;
         R.n_loops = (uint32_t)r->loops.size();
+        R.init_size = (uint32_t)r->init.size();
         std::memcpy(stage.data() + o_reg + (size_t)i * sizeof(dsr_dregion), &R, sizeof(R));
         b->teams[i] = r->teams;
         b->n_red[i] = r->n_red;
@@ -1261,6 +1264,7 @@ extern "C" int dsr_autotune(dsr_batch *b, const dsr_tune *cand, int32_t n_cand, 
 namespace {
 
 struct serve_slot {
+    dsr_dregion *desc;      /* host-coherent: the slot's head (descriptor, ops, loops) */
     dsr_op *ops;            /* host-coherent */
     dsr_dloop *loops;       /* host-coherent */
     uint8_t *init;          /* host-coherent */
@@ -1336,10 +1340,9 @@ struct dsr_server {
     dsr_ctx *ctx;
     dsr_serve_cfg cfg;
     uint8_t *h_block;                 /* host-coherent: stop, start ticks,
-                                         slot descriptors, completion records  */
+                                         completion records                    */
     uint32_t *stop;
     uint64_t *start_ticks;
-    dsr_dregion *regs;
     dsr_drec *recs;
     uint8_t *h_arena;                 /* host-coherent slot arenas            */
     uint8_t *d_arena;                 /* device: partials, results, counters  */
@@ -1397,7 +1400,9 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
     *out = nullptr;
     if (ctx->device < 0) return DSR_E_STATE;
     dsr_serve_cfg c = *cfg;
-    if (c.slots == 0 || c.slots > 65536 || c.max_teams == 0 || c.slot_bytes == 0) return DSR_E_INVAL;
+    /* a ring item holds the slot and the team in 16 bits each */
+    if (c.slots == 0 || c.slots > 65536 || c.max_teams == 0 || c.max_teams > 65535 || c.slot_bytes == 0)
+        return DSR_E_INVAL;
     if (c.ring_items == 0) c.ring_items = 1u << 16;
     if (c.ring_items & (c.ring_items - 1)) return DSR_E_INVAL;
     if ((uint64_t)c.slots * c.max_teams > c.ring_items) return DSR_E_INVAL;
@@ -1425,7 +1430,7 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
         K = serve_class{};
         K.slab = c.n_classes ? c.class_slab[k] : t.lds_slab_bytes;
         if (K.slab & 15u) return DSR_E_INVAL;
-        const uint64_t lds = (uint64_t)dsr::cb_bytes(nw) + K.slab + DSR_SERVE_LDS_BYTES;
+        const uint64_t lds = (uint64_t)dsr::cb_bytes(nw) + K.slab + DSR_SERVE_AREA_BYTES;
         if (lds > lds_max) return DSR_E_LDS;
         K.lds_bytes = (uint32_t)lds;
         uint32_t grid = c.n_classes ? c.class_grid[k] : t.grid;
@@ -1465,13 +1470,13 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
         K.lds_used = 0;
         K.lds_budget = (uint64_t)K.grid * K.slab * c.budget_pct / 100;
     }
-    /* shared host-coherent block: stop, start ticks, slot descriptors,
-     * completion records */
-    const size_t o_regs = 512;
-    const size_t o_recs = o_regs + align256((size_t)c.slots * sizeof(dsr_dregion));
+    /* shared host-coherent block: stop, start ticks, completion records;
+     * a slot's host block: its head (the layout of the device's LDS copy:
+     * descriptor, ops, loops), then its frame images */
+    const size_t o_recs = 512;
     const size_t blk = o_recs + align256((size_t)c.slots * sizeof(dsr_drec));
-    const size_t slot_h = align256(DSR_SERVE_MAX_OPS * sizeof(dsr_op)) +
-                          align256(DSR_SERVE_MAX_LOOPS * sizeof(dsr_dloop)) + align256(c.slot_bytes);
+    /* (a team reads DSR_SERVE_IMG_LDS image bytes whatever the request's size) */
+    const size_t slot_h = DSR_SERVE_SLOT_HEAD + align256(std::max<size_t>(c.slot_bytes, DSR_SERVE_IMG_LDS));
     const size_t part_b = align256((size_t)DSR_MAX_RED * c.max_teams * DSR_PART_WORDS * sizeof(uint64_t));
     const size_t slot_d = part_b + align256(sizeof(dsr_dresult));
     const size_t ctl_d = DSR_SRV_WORDS * sizeof(uint32_t);
@@ -1496,15 +1501,15 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
     }
     S->stop = (uint32_t *)(S->h_block + 64);
     S->start_ticks = (uint64_t *)(S->h_block + 128);
-    S->regs = (dsr_dregion *)(S->h_block + o_regs);
     S->recs = (dsr_drec *)(S->h_block + o_recs);
     S->slots.resize(c.slots);
     for (uint32_t i = 0; i < c.slots; ++i) {
         uint8_t *h = S->h_arena + slot_h * i;
         serve_slot &sl = S->slots[i];
-        sl.ops = (dsr_op *)h;
-        sl.loops = (dsr_dloop *)(h + align256(DSR_SERVE_MAX_OPS * sizeof(dsr_op)));
-        sl.init = h + align256(DSR_SERVE_MAX_OPS * sizeof(dsr_op)) + align256(DSR_SERVE_MAX_LOOPS * sizeof(dsr_dloop));
+        sl.desc = (dsr_dregion *)h;
+        sl.ops = (dsr_op *)(h + DSR_SERVE_OPS_AT);
+        sl.loops = (dsr_dloop *)(h + DSR_SERVE_LOOPS_AT);
+        sl.init = h + DSR_SERVE_SLOT_HEAD;
         sl.d_partials = (uint64_t *)(S->d_arena + slot_d * i);
         sl.d_result = (dsr_dresult *)(S->d_arena + slot_d * i + part_b);
         sl.busy = false;
@@ -1538,7 +1543,8 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
     for (uint32_t k = 0; k < n_cls; ++k) {
         serve_class &K = S->cls[k];
         dsr_dlaunch LP{};
-        LP.regions = S->regs;
+        LP.regions = (const dsr_dregion *)S->h_arena;
+        LP.region_stride = (uint32_t)slot_h;
         LP.items = K.items;
         LP.n_items = 0;
         LP.n_regions = c.slots;
@@ -1663,11 +1669,12 @@ extern "C" int dsr_serve_submit(dsr_server *S, dsr_region *r, void *const *outs,
     R.red_kind_mask = r->red_kind_mask;
     R.tag = tk;
     R.n_loops = (uint32_t)r->loops.size();
-    S->regs[k] = R;
+    R.init_size = (uint32_t)r->init.size();
+    *sl.desc = R;
+    uint64_t *ring = (uint64_t *)K.items;
     for (int32_t t = 0; t < r->teams; ++t) {
-        const uint32_t it = (K.pub + (uint32_t)t) & (S->cfg.ring_items - 1);
-        K.items[2 * it] = k;
-        K.items[2 * it + 1] = (uint32_t)t;
+        const uint32_t seq = K.pub + (uint32_t)t;
+        ring[seq & (S->cfg.ring_items - 1)] = ((uint64_t)seq << 32) | ((uint64_t)k << 16) | (uint32_t)t;
     }
     sl.busy = true;
     sl.ticket = tk;

@@ -76,18 +76,34 @@ struct dsr_dregion {
     uint32_t red_kind_mask; /* bit r set: reduction r is FMA_CHAIN (exact fp64) */
     uint64_t tag;           /* served form: request ticket written on completion */
     uint32_t n_loops;
-    uint32_t pad;
+    uint32_t init_size;     /* bytes of the init blob                          */
 };
 
 /* Program parts a single-region launch carries in its kernel arguments. */
 #define DSR_INLINE_OPS 4
 #define DSR_INLINE_IMG 512
 
-/* Served form limits (a request's program is copied into LDS per item). */
+/* Served form limits (a request's program is copied into LDS per item).  A
+ * request slot in host memory starts with the same 1216 bytes as the LDS
+ * copy: its descriptor (128 B reserved), DSR_SERVE_MAX_OPS ops at 128 and
+ * DSR_SERVE_MAX_LOOPS loop descriptors at 896, so a team copies all of it
+ * in one round of loads; the frame images follow at DSR_SERVE_SLOT_HEAD.
+ * A ring item is one 64-bit word: the item's position in the ring's
+ * sequence (upper 32 bits), the slot (bits 16-31) and the team (bits 0-15),
+ * so a reader can tell a stale word from the item it waits for. */
 #define DSR_SERVE_MAX_OPS 16
 #define DSR_SERVE_MAX_LOOPS 4
-#define DSR_SERVE_LDS_BYTES (128 + DSR_SERVE_MAX_OPS * 48 + DSR_SERVE_MAX_LOOPS * 80)
+#define DSR_SERVE_OPS_AT 128
+#define DSR_SERVE_LOOPS_AT (DSR_SERVE_OPS_AT + DSR_SERVE_MAX_OPS * 48)
+#define DSR_SERVE_LDS_BYTES (DSR_SERVE_LOOPS_AT + DSR_SERVE_MAX_LOOPS * 80)
+#define DSR_SERVE_SLOT_HEAD 1280
+/* The first DSR_SERVE_IMG_LDS bytes of the frame images come in the same
+ * round; a request whose whole init blob fits initialises its frames from
+ * that LDS copy.  The LDS area a server team reserves after its stack: */
+#define DSR_SERVE_IMG_LDS 1024
+#define DSR_SERVE_AREA_BYTES (DSR_SERVE_SLOT_HEAD + DSR_SERVE_IMG_LDS)
 static_assert(sizeof(dsr_op) == 48 && sizeof(dsr_dloop) == 80, "served LDS copy layout");
+static_assert(DSR_SERVE_LDS_BYTES <= DSR_SERVE_SLOT_HEAD && DSR_SERVE_LDS_BYTES % 16 == 0, "served slot head");
 
 /* Served form: completion record of one request slot, in host-coherent
  * memory.  The device fills it and then stores `seq` (the request ticket)
@@ -108,7 +124,8 @@ struct dsr_drec {
  * leave resets the counters. */
 struct dsr_dlaunch {
     const dsr_dregion *regions;
-    const uint32_t *items;  /* [n_items][2] = {region, team}, or null */
+    const uint32_t *items;  /* [n_items][2] = {region, team}, or null; served
+                               form: the ring of 64-bit items */
     uint32_t n_items;
     uint32_t n_regions;
     uint32_t *counter;      /* [0] next item, [1] workgroups finished;
@@ -120,7 +137,8 @@ struct dsr_dlaunch {
     const uint32_t *stop;      /* host-coherent: nonzero = close the server */
     dsr_drec *recs;            /* host-coherent completion records, per slot */
     uint32_t ring_mask;        /* ring capacity - 1 (power of two)          */
-    uint32_t pad2;
+    uint32_t region_stride;    /* served form: bytes between request slots
+                                  (regions[] is then the first slot)       */
     uint32_t *closing;         /* host-coherent: set by the device when it
                                   starts to close the server                */
     uint32_t *final_items;     /* host-coherent: 1 + the published count the

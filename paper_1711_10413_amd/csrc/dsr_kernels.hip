@@ -1763,9 +1763,10 @@ __device__ __forceinline__ void close_server(const dsr_dlaunch &LP, uint32_t rea
  * item nobody will publish to it, and no claimed item is lost.  Nothing
  * here waits for another workgroup, so the server does not rely on its
  * whole grid being resident at once. */
-__device__ __forceinline__ bool wait_item(const dsr_dlaunch &LP, uint32_t it, uint32_t lane)
+__device__ __forceinline__ bool wait_item(const dsr_dlaunch &LP, uint32_t it, uint32_t lane, uint64_t &item)
 {
     uint32_t ok = 0;
+    const uint64_t *ring = (const uint64_t *)LP.items;
     if (lane == 0) {
         uint32_t *ctr = LP.counter;
         uint32_t nap = 0;
@@ -1790,7 +1791,10 @@ __device__ __forceinline__ bool wait_item(const dsr_dlaunch &LP, uint32_t it, ui
             }
             if (st == 0) {
                 if (it == pub) {
+                    /* the item is read in the same round as the host's count;
+                     * its sequence field tells whether it is already this one */
                     const uint32_t h = __hip_atomic_load(LP.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    item = __hip_atomic_load(ring + (it & LP.ring_mask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     if (h != pub) {
                         __hip_atomic_fetch_max(ctr + DSR_SRV_PUB, h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         ok = 1;
@@ -1830,6 +1834,13 @@ __device__ __forceinline__ bool wait_item(const dsr_dlaunch &LP, uint32_t it, ui
     }
     ok = __shfl((int)ok, 0, 64);
     if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (ok && lane == 0) {
+        /* published before the count that was seen: a word still holding an
+         * older sequence is read again (bounded, so a broken ring cannot
+         * hold the workgroup) */
+        for (uint32_t k = 0; (uint32_t)(item >> 32) != it && k < (1u << 22); ++k)
+            item = __hip_atomic_load(ring + (it & LP.ring_mask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
     return ok != 0;
 }
 
@@ -1843,32 +1854,40 @@ __device__ __forceinline__ dsr_dregion *serve_area(const team_t &T)
     return (dsr_dregion *)(T.stack_lds + T.lds_cap);
 }
 
-__device__ __forceinline__ void copy_words_sys(uint32_t *dst, const uint32_t *src, uint32_t words,
-                                               uint32_t lane)
+__device__ __forceinline__ const dsr_dregion &stage_request(team_t &T, const uint8_t *slot)
 {
-    for (uint32_t k = lane; k < words; k += 64)
-        dst[k] = __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
-__device__ __forceinline__ const dsr_dregion &stage_request(team_t &T, const dsr_dregion *src)
-{
+    /* the slot's head has the layout of this LDS area: one round of loads
+     * brings the descriptor, the ops and the loop descriptors together */
     dsr_dregion *Rl = serve_area(T);
-    uint8_t *ops_l = (uint8_t *)Rl + 128;
-    uint8_t *loops_l = ops_l + DSR_SERVE_MAX_OPS * 48;
-    copy_words_sys((uint32_t *)Rl, (const uint32_t *)src, sizeof(dsr_dregion) / 4, T.lane);
+    uint8_t *ops_l = (uint8_t *)Rl + DSR_SERVE_OPS_AT;
+    uint8_t *loops_l = (uint8_t *)Rl + DSR_SERVE_LOOPS_AT;
+    {
+        /* every load issued before any store: one host round trip for the
+         * head and the first DSR_SERVE_IMG_LDS bytes of the frame images */
+        constexpr uint32_t NW = DSR_SERVE_AREA_BYTES / 8, PER = (NW + 63) / 64;
+        const uint64_t *src = (const uint64_t *)slot;
+        uint64_t *dst = (uint64_t *)Rl;
+        uint64_t v[PER];
+#pragma unroll
+        for (uint32_t r = 0; r < PER; ++r) {
+            const uint32_t k = T.lane + 64u * r;
+            v[r] = k < NW ? __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : 0ull;
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < PER; ++r) {
+            const uint32_t k = T.lane + 64u * r;
+            if (k < NW) dst[k] = v[r];
+        }
+    }
     wave_sync();
     const uint32_t n_ops = min(uniform(Rl->n_ops), (uint32_t)DSR_SERVE_MAX_OPS);
-    const uint32_t n_loops = min(uniform(Rl->n_loops), (uint32_t)DSR_SERVE_MAX_LOOPS);
-    const dsr_op *ops_h = Rl->ops;
-    const dsr_dloop *loops_h = Rl->loops;
-    wave_sync();
-    copy_words_sys((uint32_t *)ops_l, (const uint32_t *)ops_h, n_ops * sizeof(dsr_op) / 4, T.lane);
-    copy_words_sys((uint32_t *)loops_l, (const uint32_t *)loops_h, n_loops * sizeof(dsr_dloop) / 4, T.lane);
+    const bool img_here = uniform(Rl->init_size) <= DSR_SERVE_IMG_LDS;
     wave_sync();
     if (T.lane == 0) {
         Rl->ops = (const dsr_op *)ops_l;
         Rl->loops = (const dsr_dloop *)loops_l;
         Rl->n_ops = n_ops;
+        if (img_here) Rl->init = (const uint8_t *)Rl + DSR_SERVE_SLOT_HEAD;
     }
     wave_sync();
     return *Rl;
@@ -1909,12 +1928,11 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
                 if (LP.published) {
                     /* served form: wait until the host has published item
                      * `it`; leave once the server has closed below it */
-                    if (!wait_item(LP, it, T.lane)) break;
-                    const uint32_t k = it & LP.ring_mask;
-                    region = uniform(__hip_atomic_load(&LP.items[2 * k], __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_SYSTEM));
-                    team = uniform(__hip_atomic_load(&LP.items[2 * k + 1], __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_SYSTEM));
+                    uint64_t item = 0;
+                    if (!wait_item(LP, it, T.lane, item)) break;
+                    const uint64_t w = (uint64_t)__shfl((long long)item, 0, 64);
+                    region = uniform((uint32_t)(w >> 16) & 0xffffu);
+                    team = uniform((uint32_t)w & 0xffffu);
                 } else {
                     if (it >= LP.n_items) break;
                     if (it == 0 && LP.done_ts && T.lane == 0) LP.done_ts[LP.n_regions] = wall_clock64();
@@ -1923,7 +1941,8 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
                 }
                 team_reset(T);
             }
-            const dsr_dregion &R = (!lean && C.serve) ? stage_request(T, LP.regions + region)
+            const dsr_dregion &R = (!lean && C.serve)
+                                       ? stage_request(T, (const uint8_t *)LP.regions + (uint64_t)region * LP.region_stride)
                                                         : ((lean && LP.has_single) ? LP.single : LP.regions[region]);
             run_program<VARIANT>(T, R, C, LP, single, region, team, barriers, inner_pushes);
             GLB uint32_t *tr = (single && C.trace && R.trace) ? (GLB uint32_t *)(R.trace + (uint64_t)team * DSR_TRACE_WORDS) : nullptr;
