@@ -464,7 +464,7 @@ typedef struct dsr_serve_cfg {
                                  32 when only one fits per CU)                    */
     uint32_t slots;           /* requests in flight at most                      */
     uint32_t slot_bytes;      /* frame-image bytes per slot                      */
-    uint32_t max_teams;       /* teams per request at most                       */
+    uint32_t max_teams;       /* teams per request at most (1 .. 65535)          */
     uint32_t ring_items;      /* item ring capacity (power of two)               */
     uint32_t idle_ms;         /* server exits after this long without new work  */
     uint32_t budget_pct;      /* admission budget, percent of the resident stacks
@@ -508,7 +508,11 @@ typedef struct dsr_done {
  * submits failing with DSR_E_STATE.  The default grid leaves room for them.
  * A device-wide synchronisation, or an allocation or free that performs
  * one, also waits for the resident kernel: allocate the buffers requests use
- * before starting the server. */
+ * before starting the server.  Fails with DSR_E_INVAL when slots is not in
+ * 1 .. 65536, max_teams not in 1 .. 65535 (a ring item holds the slot and
+ * the team in 16 bits each), slot_bytes is 0, ring_items is not a power of
+ * two or below slots * max_teams, n_classes exceeds DSR_SERVE_CLASSES or
+ * a class slab is not a multiple of 16. */
 int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_server **out);
 
 /* Submit region `program` (not launched itself; its frames all popped) (not

@@ -255,6 +255,12 @@ def test_serve_requests_match_oracle(setup):
 def test_serve_admission(setup):
     ctx, insts, xs, ys, regs = setup
     say("serve admission")
+    # a ring item holds the team in 16 bits; the slot count is bounded too
+    for kw in (dict(max_teams=65536, ring_items=1 << 17, slots=1), dict(slots=65537),
+               dict(ring_items=3000)):
+        with pytest.raises(D.DsrError) as e:
+            D.dsr_serve_start(ctx, **kw)
+        assert e.value.code == D.DSR_E_INVAL, kw
     srv = D.dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=32768, slots=4, slot_bytes=40960,
                             max_teams=64, idle_ms=20000)
     try:
