@@ -613,6 +613,9 @@ def run_served(torch, np, D, W, stream, rates, seconds, pool=1000, seed=4, slots
     # a request's teams: one per 16384 elements (up to 64), for latency
     chunk = 16384
     regs, insts = build_programs(D, W, ctx, Ls, Fs, offs, seed, x.data_ptr(), y.data_ptr(), chunk)
+    # the templates' frame images resident in HBM, as the batch's are
+    for r in regs:
+        D.dsr_region_freeze(r)
     slot_y = [torch.empty(1 << 20, dtype=torch.float64, device=dev) for _ in range(slots)]
     torch.cuda.synchronize()
     def oracle_y(q):

@@ -308,6 +308,17 @@ int dsr_region_elapsed(dsr_region *r, float *ms);
 /* Release a region's host and device memory (syncs its last launch). */
 int dsr_region_free(dsr_region *r);
 
+/* Upload a finished region's program and frame images to the device
+ * without launching it (what its first dsr_launch does; not in the paper):
+ * the program can no longer change.  A served request of a frozen region
+ * initialises frames larger than 1 KiB from this device copy instead of
+ * from its request slot in host memory, so keep the region until its
+ * requests have completed.  Synchronous (it allocates device memory): call
+ * it before dsr_serve_start.  DSR_E_LIVE while a frame is live, DSR_E_INVAL
+ * for more teams than max_teams, DSR_E_STATE for a host-only context,
+ * DSR_E_NOMEM or DSR_E_HIP from the device.  Freezing twice is a no-op. */
+int dsr_region_freeze(dsr_region *r);
+
 /* ---- launch without allocation --------------------------------------------
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.

@@ -554,6 +554,20 @@ static dsr_dconfig make_dconfig(const dsr_ctx *c, uint32_t wg, uint32_t lds_slab
     return C;
 }
 
+extern "C" int dsr_region_freeze(dsr_region *r)
+{
+    if (!r) return DSR_E_INVAL;
+    if (!r->live.empty()) return DSR_E_LIVE;
+    if (r->ctx->device < 0) return DSR_E_STATE;
+    if ((uint64_t)r->teams > r->ctx->cfg.max_teams) return DSR_E_INVAL;
+    if (!r->frozen) {
+        const int rc = upload(r);
+        if (rc) return rc;
+        r->frozen = true;
+    }
+    return DSR_OK;
+}
+
 extern "C" int dsr_launch(dsr_region *r, void *stream)
 {
     if (!r) return DSR_E_INVAL;
@@ -747,6 +761,8 @@ extern "C" int dsr_launch_static(dsr_region *r, dsr_result_rec *result, void *st
     R.red_kind_mask = r->red_kind_mask;
     R.n_loops = (uint32_t)r->loops.size();
     R.init_size = (uint32_t)r->init.size();
+    R.relay = nullptr;
+    R.relay_flag = nullptr;
     if (hipMemcpyAsync(ws + L.desc, &R, sizeof(R), hipMemcpyHostToDevice, s) != hipSuccess) return DSR_E_HIP;
     if (!r->ops.empty() &&
         hipMemcpyAsync(ws + L.ops, r->ops.data(), r->ops.size() * sizeof(dsr_op), hipMemcpyHostToDevice, s) !=
@@ -1270,6 +1286,8 @@ struct serve_slot {
     uint8_t *init;          /* host-coherent */
     uint64_t *d_partials;   /* device */
     dsr_dresult *d_result;  /* device */
+    uint8_t *d_img;         /* device: relayed frame images */
+    uint64_t *d_flag;       /* device: ticket whose images d_img holds */
     bool busy;
     uint64_t ticket;
     uint32_t first_item;    /* in its class's item ring */
@@ -1478,7 +1496,8 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
     /* (a team reads DSR_SERVE_IMG_LDS image bytes whatever the request's size) */
     const size_t slot_h = DSR_SERVE_SLOT_HEAD + align256(std::max<size_t>(c.slot_bytes, DSR_SERVE_IMG_LDS));
     const size_t part_b = align256((size_t)DSR_MAX_RED * c.max_teams * DSR_PART_WORDS * sizeof(uint64_t));
-    const size_t slot_d = part_b + align256(sizeof(dsr_dresult));
+    const size_t img_d = align256(c.slot_bytes);
+    const size_t slot_d = part_b + align256(sizeof(dsr_dresult)) + 256 + img_d;
     const size_t ctl_d = DSR_SRV_WORDS * sizeof(uint32_t);
     if (hipSetDevice(ctx->device) != hipSuccess) { delete S; return DSR_E_HIP; }
     if (hipHostMalloc((void **)&S->h_block, blk, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
@@ -1512,6 +1531,8 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
         sl.init = h + DSR_SERVE_SLOT_HEAD;
         sl.d_partials = (uint64_t *)(S->d_arena + slot_d * i);
         sl.d_result = (dsr_dresult *)(S->d_arena + slot_d * i + part_b);
+        sl.d_flag = (uint64_t *)(S->d_arena + slot_d * i + part_b + align256(sizeof(dsr_dresult)));
+        sl.d_img = S->d_arena + slot_d * i + part_b + align256(sizeof(dsr_dresult)) + 256;
         sl.busy = false;
         sl.cls = 0;
         S->free_slots.push_back(c.slots - 1 - i);
@@ -1654,12 +1675,16 @@ extern "C" int dsr_serve_submit(dsr_server *S, dsr_region *r, void *const *outs,
     for (int32_t i = 0; i < n_outs; ++i)
         if (outs[i]) L[i].out = outs[i];
     if (!L.empty()) std::memcpy(sl.loops, L.data(), L.size() * sizeof(dsr_dloop));
-    if (!r->init.empty()) std::memcpy(sl.init, r->init.data(), r->init.size());
+    /* images up to 1 KiB travel in the slot (the team stages them with the
+     * program); larger ones of a frozen region are read from its device
+     * copy */
+    const bool dev_img = r->init.size() > DSR_SERVE_IMG_LDS && r->frozen && r->d_init;
+    if (!r->init.empty() && !dev_img) std::memcpy(sl.init, r->init.data(), r->init.size());
     const uint64_t tk = S->next_ticket++;
     dsr_dregion R{};
     R.ops = sl.ops;
     R.loops = sl.loops;
-    R.init = sl.init;
+    R.init = dev_img ? r->d_init : sl.init;
     R.partials = sl.d_partials;
     R.result = sl.d_result;
     R.trace = nullptr;
@@ -1670,6 +1695,12 @@ extern "C" int dsr_serve_submit(dsr_server *S, dsr_region *r, void *const *outs,
     R.tag = tk;
     R.n_loops = (uint32_t)r->loops.size();
     R.init_size = (uint32_t)r->init.size();
+    /* tickets start at 1, and the flags at 0 */
+    if (!dev_img && r->teams > 1 && r->init.size() > DSR_SERVE_IMG_LDS &&
+        (uint64_t)r->teams * r->init.size() >= DSR_SERVE_RELAY_MIN) {
+        R.relay = sl.d_img;
+        R.relay_flag = sl.d_flag;
+    }
     *sl.desc = R;
     uint64_t *ring = (uint64_t *)K.items;
     for (int32_t t = 0; t < r->teams; ++t) {

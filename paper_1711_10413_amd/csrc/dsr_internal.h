@@ -77,6 +77,11 @@ struct dsr_dregion {
     uint64_t tag;           /* served form: request ticket written on completion */
     uint32_t n_loops;
     uint32_t init_size;     /* bytes of the init blob                          */
+    /* served form: a device buffer the request's team 0 copies the init
+     * blob into from the host slot (null: every team reads the slot), and
+     * the word it then sets to `tag` */
+    uint8_t *relay;
+    uint64_t *relay_flag;
 };
 
 /* Program parts a single-region launch carries in its kernel arguments. */
@@ -102,7 +107,11 @@ struct dsr_dregion {
  * that LDS copy.  The LDS area a server team reserves after its stack: */
 #define DSR_SERVE_IMG_LDS 1024
 #define DSR_SERVE_AREA_BYTES (DSR_SERVE_SLOT_HEAD + DSR_SERVE_IMG_LDS)
+/* A request whose teams would read at least this many image bytes from the
+ * host slot in all has them relayed through device memory by its team 0. */
+#define DSR_SERVE_RELAY_MIN (64u * 1024u)
 static_assert(sizeof(dsr_op) == 48 && sizeof(dsr_dloop) == 80, "served LDS copy layout");
+static_assert(sizeof(dsr_dregion) <= DSR_SERVE_OPS_AT, "served descriptor fits the slot head");
 static_assert(DSR_SERVE_LDS_BYTES <= DSR_SERVE_SLOT_HEAD && DSR_SERVE_LDS_BYTES % 16 == 0, "served slot head");
 
 /* Served form: completion record of one request slot, in host-coherent

@@ -1854,7 +1854,52 @@ __device__ __forceinline__ dsr_dregion *serve_area(const team_t &T)
     return (dsr_dregion *)(T.stack_lds + T.lds_cap);
 }
 
-__device__ __forceinline__ const dsr_dregion &stage_request(team_t &T, const uint8_t *slot)
+/* Served form, large images: team 0 of the request copies the init blob
+ * from the host slot into the slot's device buffer, and the other teams
+ * wait for it there instead of each reading the whole blob across the
+ * host link (64 teams of a 32 KiB image would move 2 MiB over it).  The
+ * flag holds the ticket whose images the buffer holds; tickets are unique,
+ * so it is never cleared.  A team that does not see its ticket within the
+ * spin bound reads the host slot, which is always correct. */
+__device__ __forceinline__ bool relay_images(const dsr_dregion *Rl, uint32_t team, uint32_t lane)
+{
+    GLB uint8_t *dst = (GLB uint8_t *)Rl->relay;
+    GLB uint64_t *flag = (GLB uint64_t *)Rl->relay_flag;
+    const uint64_t tag = Rl->tag;
+    if (team == 0) {
+        /* the slot is padded past the blob to a multiple of 256 bytes */
+        const uint32_t nv = (Rl->init_size + 15u) >> 4;
+        const i32x4 *src = (const i32x4 *)Rl->init;
+        GLB i32x4 *d4 = (GLB i32x4 *)dst;
+        for (uint32_t k0 = lane; k0 < nv; k0 += 512) {
+            i32x4 v[8];
+#pragma unroll
+            for (uint32_t u = 0; u < 8; ++u) {
+                const uint32_t k = k0 + 64u * u;
+                v[u] = src[min(k, nv - 1)];
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 8; ++u)
+                if (k0 + 64u * u < nv) d4[k0 + 64u * u] = v[u];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) __hip_atomic_store(flag, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+    }
+    uint32_t seen = 0;
+    if (lane == 0) {
+        for (uint32_t spin = 0; spin < (1u << 20); ++spin) {
+            if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == tag) {
+                seen = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    return __shfl((int)seen, 0, 64) != 0;
+}
+
+__device__ __forceinline__ const dsr_dregion &stage_request(team_t &T, const uint8_t *slot, uint32_t team)
 {
     /* the slot's head has the layout of this LDS area: one round of loads
      * brings the descriptor, the ops and the loop descriptors together */
@@ -1882,12 +1927,17 @@ __device__ __forceinline__ const dsr_dregion &stage_request(team_t &T, const uin
     wave_sync();
     const uint32_t n_ops = min(uniform(Rl->n_ops), (uint32_t)DSR_SERVE_MAX_OPS);
     const bool img_here = uniform(Rl->init_size) <= DSR_SERVE_IMG_LDS;
+    /* (the host asks for a relay only for blobs larger than the LDS copy) */
+    const bool relayed = !img_here && Rl->relay != nullptr && relay_images(Rl, team, T.lane);
+    /* the relayed bytes are read with plain loads below: acquire */
+    if (relayed) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     wave_sync();
     if (T.lane == 0) {
         Rl->ops = (const dsr_op *)ops_l;
         Rl->loops = (const dsr_dloop *)loops_l;
         Rl->n_ops = n_ops;
         if (img_here) Rl->init = (const uint8_t *)Rl + DSR_SERVE_SLOT_HEAD;
+        if (relayed) Rl->init = Rl->relay;
     }
     wave_sync();
     return *Rl;
@@ -1942,7 +1992,7 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
                 team_reset(T);
             }
             const dsr_dregion &R = (!lean && C.serve)
-                                       ? stage_request(T, (const uint8_t *)LP.regions + (uint64_t)region * LP.region_stride)
+                                       ? stage_request(T, (const uint8_t *)LP.regions + (uint64_t)region * LP.region_stride, team)
                                                         : ((lean && LP.has_single) ? LP.single : LP.regions[region]);
             run_program<VARIANT>(T, R, C, LP, single, region, team, barriers, inner_pushes);
             GLB uint32_t *tr = (single && C.trace && R.trace) ? (GLB uint32_t *)(R.trace + (uint64_t)team * DSR_TRACE_WORDS) : nullptr;

@@ -59,7 +59,7 @@ EXPORTS = ("dsr_init", "dsr_destroy", "dsr_region_begin", "dsr_push", "dsr_publi
            "dsr_serve_replay", "dsr_serve_stop", "dsr_occupancy_model", "dsr_region_occupancy",
            "dsr_publish_list", "dsr_control_bytes", "dsr_serve_status", "dsr_launch_static",
            "dsr_static_bytes", "dsr_stream_ceiling", "dsr_autotune_plan",
-           "dsr_serve_class_for")
+           "dsr_serve_class_for", "dsr_region_freeze")
 
 
 class dsr_ref(C.Structure):
@@ -202,6 +202,7 @@ def lib():
             "dsr_region_trace": [P, i32, C.POINTER(u32), u32],
             "dsr_region_elapsed": [P, C.POINTER(C.c_float)],
             "dsr_region_free": [P],
+            "dsr_region_freeze": [P],
             "dsr_batch_create": [P, C.POINTER(P), i32, C.POINTER(P)],
             "dsr_batch_tune": [P, C.POINTER(dsr_tune)],
             "dsr_batch_get_tune": [P, C.POINTER(dsr_tune)],
@@ -393,6 +394,11 @@ def dsr_region_elapsed(region):
 
 def dsr_region_free(region):
     return _check(lib().dsr_region_free(region), "dsr_region_free")
+
+
+def dsr_region_freeze(region):
+    """Upload the region's program and images without launching it."""
+    return _check(lib().dsr_region_freeze(region), "dsr_region_freeze")
 
 
 # ---- batched form -----------------------------------------------------------

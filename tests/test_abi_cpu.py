@@ -274,6 +274,21 @@ def test_static_launch_host_checks():
     D.dsr_destroy(ctx)
 
 
+def test_freeze_host_checks():
+    """Freezing refuses a live frame and a host-only context before any
+    device work."""
+    ctx = host_ctx(wg_size=256, lds_slab_bytes=4096, hbm_slab_bytes=65536, max_teams=4)
+    r = D.dsr_region_begin(ctx, 4)
+    f = D.dsr_push(r, 24, D.affine_xor_frame(1, 2, 3, 4))
+    assert D.lib().dsr_region_freeze(r) == D.DSR_E_LIVE
+    D.dsr_publish(r, f, D.DSR_BODY_AFFINE_XOR, 1024, out=16)
+    D.dsr_pop(r, f)
+    assert D.lib().dsr_region_freeze(r) == D.DSR_E_STATE
+    assert D.lib().dsr_region_freeze(None) == D.DSR_E_INVAL
+    D.dsr_region_free(r)
+    D.dsr_destroy(ctx)
+
+
 def test_deref_only_for_scalar_lists():
     """Per-batch reads through the list (deref) exist for the list publish of
     scalars only: a frame publish or a list with an array is refused."""

@@ -102,6 +102,12 @@ def setup():
     xs = [torch.from_numpy(x).cuda() for _, x, _, _, _ in insts]
     ys = [torch.zeros(ins.L, dtype=torch.float64, device="cuda") for ins, *_ in insts]
     regs = programs(ctx, insts, 8192, xs, ys)
+    # half the templates frozen: their requests initialise frames over 1 KiB
+    # from the device copy; the others' come from the host slot, directly
+    # or relayed through device memory by team 0 when their teams would
+    # read 64 KiB or more from it
+    for r in regs[::2]:
+        D.dsr_region_freeze(r)
     torch.cuda.current_stream().synchronize()
     yield ctx, insts, xs, ys, regs
     for r in regs:
