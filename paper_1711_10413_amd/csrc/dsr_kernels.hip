@@ -1664,14 +1664,20 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &RD, uint32_t team
     if (tr && lane == 0) tr[92] = (uint32_t)wall_clock64();
     GLB dsr_dresult *res = (GLB dsr_dresult *)R.result;
     uint32_t prev = 0;
-    if (lane == 0)
-        prev = __hip_atomic_fetch_add(&res->group[g * 16], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    prev = uniform((uint32_t)__shfl((int)prev, 0, 64));
-    if (tr && lane == 0) tr[93] = (uint32_t)wall_clock64();
-    if (prev != in_group - 1) return;
-    /* the last arriver of a group reads the others' partials: acquire */
-    if (DSR_ARRIVE_FENCE) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (lane == 0) __hip_atomic_store(&res->group[g * 16], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    /* a region of one team has nothing to arrive at: this wave wrote every
+     * partial and the error word itself */
+    if (R.teams > 1) {
+        if (lane == 0)
+            prev = __hip_atomic_fetch_add(&res->group[g * 16], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        prev = uniform((uint32_t)__shfl((int)prev, 0, 64));
+        if (tr && lane == 0) tr[93] = (uint32_t)wall_clock64();
+        if (prev != in_group - 1) return;
+        /* the last arriver of a group reads the others' partials: acquire */
+        if (DSR_ARRIVE_FENCE) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (lane == 0) __hip_atomic_store(&res->group[g * 16], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (tr && lane == 0) {
+        tr[93] = (uint32_t)wall_clock64();
+    }
     if (ngroups > 1) {
         if (group_sums) {
             for (uint32_t r = 0; r < R.n_red; ++r) {
