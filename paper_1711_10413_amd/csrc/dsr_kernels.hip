@@ -1611,35 +1611,39 @@ __device__ __forceinline__ i192 sum_partials(const uint64_t *base, uint32_t cnt,
 
 /* Last team: the region's reductions from the (group) partials, exact in
  * 192-bit integers, rounded once for fp64. */
-__device__ __forceinline__ void combine_teams(const region_sums &R, uint32_t cnt, uint32_t stride, uint32_t lane)
+__device__ __forceinline__ void combine_teams(const region_sums &R, uint32_t cnt, uint32_t stride, uint32_t lane,
+                                              dsr_drec *rec)
 {
     for (uint32_t r = 0; r < R.n_red; ++r) {
         const i192 s = sum_partials(R.partials + (uint64_t)r * R.teams * DSR_PART_WORDS, cnt, stride, lane);
         if (lane == 0) {
             GLB dsr_dresult *res = (GLB dsr_dresult *)R.result;
+            const double f = ((R.red_kind_mask >> r) & 1u) ? fixed_to_double(s) : (double)(int64_t)s.w0;
             res->fixed[r][0] = s.w0;
             res->fixed[r][1] = s.w1;
             res->fixed[r][2] = s.w2;
             res->i64[r] = (int64_t)s.w0;
-            res->f64[r] = ((R.red_kind_mask >> r) & 1u) ? fixed_to_double(s) : (double)(int64_t)s.w0;
+            res->f64[r] = f;
+            /* served form: the completion record gets the same values
+             * directly, not read back from the result block */
+            if (rec && r < DSR_MAX_RED) {
+                rec->fixed[r][0] = s.w0;
+                rec->fixed[r][1] = s.w1;
+                rec->fixed[r][2] = s.w2;
+                rec->i64[r] = (int64_t)s.w0;
+                rec->f64[r] = f;
+            }
         }
     }
 }
 
-/* Served form: copy a finished region's result into its host-coherent
- * completion record, then release the ticket. */
-__device__ __forceinline__ void publish_record(const dsr_dregion &R, dsr_drec *rec, uint32_t lane)
+/* Served form: finish a region's host-coherent completion record (its
+ * sums are already there) and release the ticket; the system-scope release
+ * also writes this XCD's L2 back, outputs included. */
+__device__ __forceinline__ void publish_record(const dsr_dregion &R, dsr_drec *rec, int32_t err, uint32_t lane)
 {
     if (lane != 0) return;
-    drain_memory();                      /* the result block is written */
-    for (uint32_t r = 0; r < R.n_red && r < DSR_MAX_RED; ++r) {
-        rec->f64[r] = R.result->f64[r];
-        rec->i64[r] = R.result->i64[r];
-        rec->fixed[r][0] = R.result->fixed[r][0];
-        rec->fixed[r][1] = R.result->fixed[r][1];
-        rec->fixed[r][2] = R.result->fixed[r][2];
-    }
-    rec->status = R.result->final_error;
+    rec->status = err;
     rec->n_red = R.n_red;
     rec->ticks = wall_clock64();
     __hip_atomic_store(&rec->seq, R.tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1704,15 +1708,15 @@ __device__ __forceinline__ void finish_team(const dsr_dregion &RD, uint32_t team
     int32_t err = 0;
     if (lane == 0) err = __hip_atomic_exchange(&res->error, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (lane < DSR_MAX_LOOPS) __hip_atomic_store(&res->claim[lane], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (ngroups > 1 && group_sums) combine_teams(R, ngroups, gsize, lane);
-    else combine_teams(R, R.teams, 1, lane);
+    if (ngroups > 1 && group_sums) combine_teams(R, ngroups, gsize, lane, rec);
+    else combine_teams(R, R.teams, 1, lane, rec);
     if (lane == 0) {
         res->final_error = err;
         __hip_atomic_fetch_add(&res->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (done_ts) *done_ts = wall_clock64();
         if (tr) tr[95] = (uint32_t)wall_clock64();
     }
-    if (rec) publish_record(RD, rec, lane);
+    if (rec) publish_record(RD, rec, err, lane);
 }
 
 /* Served form: close the server (one workgroup does it; see wait_item).
@@ -2003,7 +2007,9 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
             run_program<VARIANT>(T, R, C, LP, single, region, team, barriers, inner_pushes);
             GLB uint32_t *tr = (single && C.trace && R.trace) ? (GLB uint32_t *)(R.trace + (uint64_t)team * DSR_TRACE_WORDS) : nullptr;
             if (tr && T.lane == 0) tr[87] = (uint32_t)wall_clock64();
-            if (!lean && C.serve) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); /* outputs out of L2 */
+            /* outputs out of L2 before the arrival; a request of one team
+             * has its completion record's system-scope release do it */
+            if (!lean && C.serve && R.teams > 1) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             /* the 1024-thread instance reads fewer partials per round */
             finish_team(R, team, T.lane, (LP.done_ts && !LP.published) ? LP.done_ts + region : nullptr,
                         (!lean && LP.recs) ? LP.recs + region : nullptr, tr);
