@@ -592,6 +592,10 @@ typedef struct dsr_serve_stat {
      * it saw and the idle time it measured (microseconds) */
     uint32_t close_reason, close_block, close_item, close_seen;
     double close_idle_us;
+    /* requests whose frame images team 0 relayed through device memory for
+     * the other teams, and teams that stopped waiting for such a relay and
+     * read the host slot instead (a nonzero count means a relay stalled) */
+    uint32_t relays, relay_misses;
 } dsr_serve_stat;
 int dsr_serve_status(dsr_server *s, dsr_serve_stat *out);
 

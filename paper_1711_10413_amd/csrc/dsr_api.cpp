@@ -1345,6 +1345,7 @@ struct serve_class {
     uint32_t *published;
     uint32_t *closing;                /* device: the class is closing           */
     uint32_t *final_items;            /* device: 1 + items served (0 = open)    */
+    uint32_t *relays;                 /* device: relayed requests, relay time-outs */
     uint32_t *wg_started;             /* per resident workgroup                 */
     uint32_t *wg_exited;
     uint32_t *items;
@@ -1551,6 +1552,7 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
         K.published = (uint32_t *)K.h_ctl;
         K.closing = (uint32_t *)(K.h_ctl + 64);
         K.final_items = (uint32_t *)(K.h_ctl + 128);
+        K.relays = (uint32_t *)(K.h_ctl + 192);
         K.wg_started = (uint32_t *)(K.h_ctl + o_wg);
         K.wg_exited = (uint32_t *)(K.h_ctl + o_wg + align256((size_t)K.grid * 4));
         K.items = (uint32_t *)(K.h_ctl + o_items);
@@ -1578,6 +1580,7 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
         LP.idle_limit = (uint64_t)c.idle_ms * 100000ull;
         LP.closing = K.closing;
         LP.final_items = K.final_items;
+        LP.relays = K.relays;
         LP.wg_started = K.wg_started;
         LP.wg_exited = K.wg_exited;
         dsr_dconfig C = make_dconfig(ctx, t.wg_size, K.slab, t.overflow_threshold, t.master_joins, 0);
@@ -1799,6 +1802,8 @@ extern "C" int dsr_serve_status(dsr_server *S, dsr_serve_stat *out)
         const uint32_t fin = __atomic_load_n(K.final_items, __ATOMIC_ACQUIRE);
         st.final_items += fin ? fin - 1 : 0;
         st.published += K.pub;
+        st.relays += __atomic_load_n(K.relays, __ATOMIC_ACQUIRE);
+        st.relay_misses += __atomic_load_n(K.relays + 1, __ATOMIC_ACQUIRE);
     }
     st.in_flight = S->in_flight;
     st.classes = (uint32_t)S->cls.size();

@@ -89,10 +89,11 @@ struct dsr_dregion {
 #define DSR_INLINE_IMG 512
 
 /* Served form limits (a request's program is copied into LDS per item).  A
- * request slot in host memory starts with the same 1216 bytes as the LDS
- * copy: its descriptor (128 B reserved), DSR_SERVE_MAX_OPS ops at 128 and
- * DSR_SERVE_MAX_LOOPS loop descriptors at 896, so a team copies all of it
- * in one round of loads; the frame images follow at DSR_SERVE_SLOT_HEAD.
+ * request slot in host memory has the layout of the LDS copy: its
+ * descriptor (128 B reserved), DSR_SERVE_MAX_OPS ops at 128,
+ * DSR_SERVE_MAX_LOOPS loop descriptors at 896 and the frame images from
+ * DSR_SERVE_SLOT_HEAD on, so a team copies the head and the images' first
+ * bytes in one round of loads.
  * A ring item is one 64-bit word: the item's position in the ring's
  * sequence (upper 32 bits), the slot (bits 16-31) and the team (bits 0-15),
  * so a reader can tell a stale word from the item it waits for. */
@@ -154,6 +155,8 @@ struct dsr_dlaunch {
                                   device serves before it leaves (0 = open)  */
     uint32_t *wg_started;      /* host-coherent, per workgroup: 1 once it runs */
     uint32_t *wg_exited;       /* host-coherent, per workgroup: 1 once it left */
+    uint32_t *relays;          /* host-coherent: [0] requests whose images team 0
+                                  relayed, [1] teams that gave up waiting */
     uint64_t *start_ts;        /* if set, block 0 stamps its start time here */
     uint64_t idle_limit;       /* close after a waiting workgroup saw the
                                   published count unchanged for this many

@@ -1871,7 +1871,8 @@ __device__ __forceinline__ dsr_dregion *serve_area(const team_t &T)
  * flag holds the ticket whose images the buffer holds; tickets are unique,
  * so it is never cleared.  A team that does not see its ticket within the
  * spin bound reads the host slot, which is always correct. */
-__device__ __forceinline__ bool relay_images(const dsr_dregion *Rl, uint32_t team, uint32_t lane)
+__device__ __forceinline__ bool relay_images(const dsr_dregion *Rl, uint32_t team, uint32_t lane,
+                                             uint32_t *count)
 {
     GLB uint8_t *dst = (GLB uint8_t *)Rl->relay;
     GLB uint64_t *flag = (GLB uint64_t *)Rl->relay_flag;
@@ -1893,7 +1894,10 @@ __device__ __forceinline__ bool relay_images(const dsr_dregion *Rl, uint32_t tea
                 if (k0 + 64u * u < nv) d4[k0 + 64u * u] = v[u];
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (lane == 0) __hip_atomic_store(flag, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) {
+            __hip_atomic_store(flag, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (count) __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
         return true;
     }
     uint32_t seen = 0;
@@ -1905,11 +1909,13 @@ __device__ __forceinline__ bool relay_images(const dsr_dregion *Rl, uint32_t tea
             }
             __builtin_amdgcn_s_sleep(2);
         }
+        if (!seen && count) __hip_atomic_fetch_add(count + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     return __shfl((int)seen, 0, 64) != 0;
 }
 
-__device__ __forceinline__ const dsr_dregion &stage_request(team_t &T, const uint8_t *slot, uint32_t team)
+__device__ __forceinline__ const dsr_dregion &stage_request(team_t &T, const uint8_t *slot, uint32_t team,
+                                                           uint32_t *relays)
 {
     /* the slot's head has the layout of this LDS area: one round of loads
      * brings the descriptor, the ops and the loop descriptors together */
@@ -1938,7 +1944,7 @@ __device__ __forceinline__ const dsr_dregion &stage_request(team_t &T, const uin
     const uint32_t n_ops = min(uniform(Rl->n_ops), (uint32_t)DSR_SERVE_MAX_OPS);
     const bool img_here = uniform(Rl->init_size) <= DSR_SERVE_IMG_LDS;
     /* (the host asks for a relay only for blobs larger than the LDS copy) */
-    const bool relayed = !img_here && Rl->relay != nullptr && relay_images(Rl, team, T.lane);
+    const bool relayed = !img_here && Rl->relay != nullptr && relay_images(Rl, team, T.lane, relays);
     /* the relayed bytes are read with plain loads below: acquire */
     if (relayed) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     wave_sync();
@@ -2002,7 +2008,8 @@ __global__ __launch_bounds__(MAXWG) void dsr_region_kernel(dsr_dlaunch LP, dsr_d
                 team_reset(T);
             }
             const dsr_dregion &R = (!lean && C.serve)
-                                       ? stage_request(T, (const uint8_t *)LP.regions + (uint64_t)region * LP.region_stride, team)
+                                       ? stage_request(T, (const uint8_t *)LP.regions + (uint64_t)region * LP.region_stride, team,
+                                                   LP.relays)
                                                         : ((lean && LP.has_single) ? LP.single : LP.regions[region]);
             run_program<VARIANT>(T, R, C, LP, single, region, team, barriers, inner_pushes);
             GLB uint32_t *tr = (single && C.trace && R.trace) ? (GLB uint32_t *)(R.trace + (uint64_t)team * DSR_TRACE_WORDS) : nullptr;

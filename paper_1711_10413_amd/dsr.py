@@ -131,7 +131,7 @@ class dsr_serve_stat(C.Structure):
                 ("closed", C.c_uint32), ("final_items", C.c_uint32), ("published", C.c_uint32),
                 ("in_flight", C.c_uint32), ("classes", C.c_uint32), ("close_reason", C.c_uint32),
                 ("close_block", C.c_uint32), ("close_item", C.c_uint32), ("close_seen", C.c_uint32),
-                ("close_idle_us", C.c_double)]
+                ("close_idle_us", C.c_double), ("relays", C.c_uint32), ("relay_misses", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -254,6 +254,10 @@ def test_serve_requests_match_oracle(setup):
         for k, (ins, x, yr, rs, fx) in enumerate(insts):
             assert np.array_equal(ys[k].cpu().numpy().view(np.uint64), yr.view(np.uint64)), k
             assert torch.equal(ys[k], extra[k])
+        # two of the unfrozen templates (6 teams, 12-16 KiB images) have
+        # their images relayed by team 0, and no team gave up waiting
+        st = D.dsr_serve_status(srv)
+        assert st["relays"] >= 2 and st["relay_misses"] == 0, st
     finally:
         D.dsr_serve_stop(srv)
 
