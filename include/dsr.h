@@ -526,14 +526,21 @@ typedef struct dsr_done {
  * a class slab is not a multiple of 16. */
 int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_server **out);
 
-/* Submit region `program` (not launched itself; its frames all popped) (not
- * in the paper).
+/* Submit region `program` (its frames all popped) (not in the paper).
  * `outs` (may be NULL) replaces the output pointer of each of its loops,
  * so one template can serve many requests with separate output buffers.
  * *ticket identifies the request in dsr_serve_poll.  The server runs on a
  * stream of its own and may start the request at once: its input and
  * output buffers must be ready (any work producing or clearing them
- * finished) when this is called. */
+ * finished) when this is called.  The program, its loop descriptors and
+ * its frame images are copied into a request slot in host memory; frame
+ * images over 1 KiB of a frozen template (dsr_region_freeze) are read from
+ * the template's device copy instead, so such a template must outlive its
+ * requests.  DSR_E_BUSY while no slot, ring space or stack budget is free
+ * (poll and retry), DSR_E_NOMEM when no LDS class can place a frame,
+ * DSR_E_INVAL for more than 16 ops, 4 loops, max_teams teams or
+ * slot_bytes of images, DSR_E_LIVE for a live frame, DSR_E_STATE once the
+ * server has closed. */
 int dsr_serve_submit(dsr_server *s, dsr_region *program, void *const *outs, int32_t n_outs,
                      uint64_t *ticket);
 
