@@ -305,15 +305,18 @@ int dsr_region_trace(dsr_region *r, int32_t team, uint32_t *buf, uint32_t n);
  * otherwise). */
 int dsr_region_elapsed(dsr_region *r, float *ms);
 
-/* Release a region's host and device memory (syncs its last launch). */
+/* Release a region's host and device memory (syncs its last launch).
+ * DSR_E_STATE (nothing released) while a server holds requests of the
+ * frozen region that read its device images and have not been collected
+ * by dsr_serve_poll (or ended by dsr_serve_stop). */
 int dsr_region_free(dsr_region *r);
 
 /* Upload a finished region's program and frame images to the device
  * without launching it (what its first dsr_launch does; not in the paper):
  * the program can no longer change.  A served request of a frozen region
  * initialises frames larger than 1 KiB from this device copy instead of
- * from its request slot in host memory, so keep the region until its
- * requests have completed.  Synchronous (it allocates device memory): call
+ * from its request slot in host memory; dsr_region_free refuses the region
+ * until those requests have been collected.  Synchronous (it allocates device memory): call
  * it before dsr_serve_start.  DSR_E_LIVE while a frame is live, DSR_E_INVAL
  * for more teams than max_teams, DSR_E_STATE for a host-only context,
  * DSR_E_NOMEM or DSR_E_HIP from the device.  Freezing twice is a no-op. */

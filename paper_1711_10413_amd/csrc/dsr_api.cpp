@@ -75,6 +75,8 @@ struct dsr_region {
     dsr_dresult *h_pin;                 /* pinned landing buffer of the result copy,
                                            allocated at the first sync */
     bool have_result;
+    uint32_t serve_refs;                /* served requests reading this frozen
+                                           region's device images, not yet polled */
     dsr_dregion static_desc;            /* descriptor copied into the workspace by
                                            dsr_launch_static */
     dsr_dregion desc;                   /* host copy of the device descriptor */
@@ -179,6 +181,7 @@ extern "C" int dsr_region_begin(dsr_ctx *ctx, int32_t teams, dsr_region **out)
     r->d_trace = nullptr;
     r->d_self = nullptr;
     r->h_pin = nullptr;
+    r->serve_refs = 0;
     r->ev0 = r->ev1 = nullptr;
     r->stream = nullptr;
     r->timed = false;
@@ -671,6 +674,7 @@ extern "C" int dsr_region_elapsed(dsr_region *r, float *ms)
 extern "C" int dsr_region_free(dsr_region *r)
 {
     if (!r) return DSR_E_INVAL;
+    if (r->serve_refs) return DSR_E_STATE;
     if (r->launched) (void)wait_launch(r);
     if (r->d_ops) hipFree(r->d_ops);
     if (r->d_loops) hipFree(r->d_loops);
@@ -1287,6 +1291,7 @@ struct serve_slot {
     uint64_t *d_partials;   /* device */
     dsr_dresult *d_result;  /* device */
     uint8_t *d_img;         /* device: relayed frame images */
+    dsr_region *tmpl;       /* frozen template whose device images the request reads */
     uint64_t *d_flag;       /* device: ticket whose images d_img holds */
     bool busy;
     uint64_t ticket;
@@ -1379,6 +1384,9 @@ namespace {
 
 void serve_free(dsr_server *S)
 {
+    /* the kernels have ended: uncollected requests read no template now */
+    for (serve_slot &sl : S->slots)
+        if (sl.busy && sl.tmpl) sl.tmpl->serve_refs--;
     for (serve_class &k : S->cls) {
         if (k.stream) (void)hipStreamDestroy(k.stream);
         if (k.h_ctl) (void)hipHostFree(k.h_ctl);
@@ -1535,6 +1543,7 @@ extern "C" int dsr_serve_start(dsr_ctx *ctx, const dsr_serve_cfg *cfg, dsr_serve
         sl.d_flag = (uint64_t *)(S->d_arena + slot_d * i + part_b + align256(sizeof(dsr_dresult)));
         sl.d_img = S->d_arena + slot_d * i + part_b + align256(sizeof(dsr_dresult)) + 256;
         sl.busy = false;
+        sl.tmpl = nullptr;
         sl.cls = 0;
         S->free_slots.push_back(c.slots - 1 - i);
     }
@@ -1604,6 +1613,8 @@ static void serve_release(dsr_server *S, uint32_t k)
 {
     serve_slot &sl = S->slots[k];
     sl.busy = false;
+    if (sl.tmpl) sl.tmpl->serve_refs--;
+    sl.tmpl = nullptr;
     S->cls[sl.cls].lds_used -= sl.lds_cost;
     S->hbm_used -= sl.hbm_cost;
     S->in_flight--;
@@ -1711,6 +1722,8 @@ extern "C" int dsr_serve_submit(dsr_server *S, dsr_region *r, void *const *outs,
         ring[seq & (S->cfg.ring_items - 1)] = ((uint64_t)seq << 32) | ((uint64_t)k << 16) | (uint32_t)t;
     }
     sl.busy = true;
+    sl.tmpl = dev_img ? r : nullptr;
+    if (dev_img) r->serve_refs++;
     sl.ticket = tk;
     sl.first_item = K.pub;
     sl.cls = (uint32_t)kc;

@@ -265,6 +265,14 @@ def test_serve_requests_match_oracle(setup):
 def test_serve_admission(setup):
     ctx, insts, xs, ys, regs = setup
     say("serve admission")
+    # a frozen template with a large image, made before the server starts
+    # (allocation and free synchronise with a resident kernel)
+    kt = next(i for i, (ins, *_) in enumerate(insts)
+              if len(D.fma_chain_frame(ins.s_i32, ins.s_f64, ins.arr)[0]) > 1024)
+    ins = insts[kt][0]
+    t = D.fma_chain_region(ctx, 2, ins.s_i32, ins.s_f64, ins.arr, ins.L, xs[kt].data_ptr(), ys[kt].data_ptr())
+    D.dsr_region_freeze(t)
+    torch.cuda.current_stream().synchronize()
     # a ring item holds the team in 16 bits; the slot count is bounded too
     for kw in (dict(max_teams=65536, ring_items=1 << 17, slots=1), dict(slots=65537),
                dict(ring_items=3000)):
@@ -295,8 +303,16 @@ def test_serve_admission(setup):
         D.dsr_serve_submit(srv, regs[4])
         done = drain(srv, 1)
         assert done[0]["f64"] == [insts[4][3]]
+        # a frozen template whose device images a request reads cannot be
+        # freed until the request has been collected (the refusal frees
+        # nothing, so it does not synchronise with the resident server)
+        D.dsr_serve_submit(srv, t)
+        assert D.lib().dsr_region_free(t) == D.DSR_E_STATE
+        done = drain(srv, 1)
+        assert done[0]["status"] == 0 and done[0]["f64"] == [insts[kt][3]]
     finally:
         D.dsr_serve_stop(srv)
+    D.dsr_region_free(t)
 
 
 def test_serve_replay_and_serial(setup):
