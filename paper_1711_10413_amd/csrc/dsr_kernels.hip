@@ -1773,6 +1773,10 @@ __device__ __forceinline__ void close_server(const dsr_dlaunch &LP, uint32_t rea
  * item nobody will publish to it, and no claimed item is lost.  Nothing
  * here waits for another workgroup, so the server does not rely on its
  * whole grid being resident at once. */
+/* Workgroups whose item is this close to the published count poll the
+ * host's count; the others poll the device copy the first of them keeps. */
+#define DSR_HOST_POLLERS 16u
+
 __device__ __forceinline__ bool wait_item(const dsr_dlaunch &LP, uint32_t it, uint32_t lane, uint64_t &item)
 {
     uint32_t ok = 0;
@@ -1800,17 +1804,25 @@ __device__ __forceinline__ bool wait_item(const dsr_dlaunch &LP, uint32_t it, ui
                 continue;
             }
             if (st == 0) {
-                if (it == pub) {
-                    /* the item is read in the same round as the host's count;
-                     * its sequence field tells whether it is already this one */
+                if (it - pub < DSR_HOST_POLLERS) {
+                    /* the workgroups holding the next items read the host's
+                     * count themselves (a later team of a request need not
+                     * wait for the device copy); the item is read in the same
+                     * round, and its sequence field tells whether it is
+                     * already this one */
                     const uint32_t h = __hip_atomic_load(LP.published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     item = __hip_atomic_load(ring + (it & LP.ring_mask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                    if (h != pub) {
+                    /* taken only while the server is still open: once a
+                     * close has begun, items count as published up to the
+                     * close's final count alone, which the closed branch
+                     * above hands out */
+                    if ((int32_t)(h - it) > 0 &&
+                        __hip_atomic_load(ctr + DSR_SRV_STATE, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT) == 0) {
                         __hip_atomic_fetch_max(ctr + DSR_SRV_PUB, h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         ok = 1;
                         break;
                     }
-                    if (__hip_atomic_load(LP.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+                    if (it == pub && __hip_atomic_load(LP.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
                         close_server(LP, 1u, it, pub, 0);
                         continue;
                     }
