@@ -1758,12 +1758,12 @@ __device__ __forceinline__ void close_server(const dsr_dlaunch &LP, uint32_t rea
  * server has closed below it (false: leave).
  *
  * The host's published count lives in host memory, so polling it crosses
- * PCIe; only the workgroup holding the next unpublished item (it == the
- * device copy of the count) polls the host, and it mirrors what it sees
- * into device memory, where every other waiting workgroup polls.  Polls
- * are relaxed (an acquire per poll would invalidate the L2 each time) and
- * back off with sleeps; once the item is seen, one agent-scope acquire
- * makes the request's device-memory inputs visible.
+ * the host link; only the DSR_HOST_POLLERS workgroups holding the next
+ * unpublished items poll the host, and they mirror what they see into
+ * device memory, where every other waiting workgroup polls.  Polls are
+ * relaxed (an acquire per poll would invalidate the L2 each time) and back
+ * off with sleeps; once the item is seen, one agent-scope acquire makes
+ * the request's device-memory inputs visible.
  *
  * Closing is one decision for the whole server, never a workgroup's own:
  * it happens when the host asks to stop, or when a waiting workgroup has
@@ -1773,8 +1773,6 @@ __device__ __forceinline__ void close_server(const dsr_dlaunch &LP, uint32_t rea
  * item nobody will publish to it, and no claimed item is lost.  Nothing
  * here waits for another workgroup, so the server does not rely on its
  * whole grid being resident at once. */
-/* Workgroups whose item is this close to the published count poll the
- * host's count; the others poll the device copy the first of them keeps. */
 #define DSR_HOST_POLLERS 16u
 
 __device__ __forceinline__ bool wait_item(const dsr_dlaunch &LP, uint32_t it, uint32_t lane, uint64_t &item)
