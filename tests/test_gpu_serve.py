@@ -377,3 +377,49 @@ def test_serve_lds_classes(setup):
         seen.add(d["lds_class"])
     assert sorted(tickets.values()) == list(range(24))
     assert set(want_cls.values()) == {0, 1}      # the instances need both classes
+
+
+def test_serve_image_size_boundaries(setup):
+    """Init blobs just under, at and just over the 1 KiB staged with the
+    program, on 1, 8 and 64 teams, from frozen and unfrozen templates:
+    LDS-staged images, images read from the host slot, images relayed by
+    team 0 (64 teams of a 1040-byte blob read 65 KiB in all) and images
+    read from the template's device copy all match the oracle."""
+    ctx = setup[0]
+    say("serve image boundaries")
+    s_i32 = np.array([3, -2, 5, 1], dtype=np.int32)
+    s_f64 = np.array([0.5, -1.25, 2.0, 0.75])
+    cases, keep = [], []
+    for alen in (232, 236, 240):                   # 1008, 1024, 1040-byte blobs
+        arr = ((np.arange(alen) * 7919) % 65536).astype(np.int32)
+        assert len(D.fma_chain_frame(s_i32, s_f64, arr)[0]) == 1008 + 16 * ((alen - 232) // 4)
+        for teams in (1, 8, 64):
+            L = teams * 16384
+            x = W.instance_x(teams * 1000 + alen, L, seed=7)
+            yr = R.fma_chain(x, s_i32, s_f64, arr)
+            for frozen in (False, True):
+                xd = torch.from_numpy(x).cuda()
+                yd = torch.zeros(L, dtype=torch.float64, device="cuda")
+                r = D.fma_chain_region(ctx, teams, s_i32, s_f64, arr, L, xd.data_ptr(), yd.data_ptr())
+                if frozen:
+                    D.dsr_region_freeze(r)
+                keep.append((xd, yd))
+                cases.append((r, yd, yr, R.exact_sum(yr), R.fixed75_sum(yr), (alen, teams, frozen)))
+    torch.cuda.current_stream().synchronize()
+    srv = D.dsr_serve_start(ctx, wg_size=256, lds_slab_bytes=32768, slots=32, slot_bytes=40960,
+                            max_teams=64, idle_ms=20000)
+    try:
+        tickets, done = {}, []
+        for c in cases:
+            tickets[submit_retry(srv, c[0], sink=done)] = c
+        done += drain(srv, len(cases) - len(done))
+        for d in done:
+            r, yd, yr, rs, fx, what = tickets[d["ticket"]]
+            assert d["status"] == 0 and d["f64"] == [rs] and d["fixed"] == [fx], what
+            assert np.array_equal(yd.cpu().numpy().view(np.uint64), yr.view(np.uint64)), what
+        st = D.dsr_serve_status(srv)
+        assert st["relays"] == 1 and st["relay_misses"] == 0, st
+    finally:
+        D.dsr_serve_stop(srv)
+    for c in cases:
+        D.dsr_region_free(c[0])
