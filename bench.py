@@ -711,7 +711,7 @@ def cpu_baseline(W, runs=5, one_core_elems=1 << 22):
     (the C calls release the interpreter lock); the slices' exact integer
     totals are added and rounded once (Python's int / int is correctly
     rounded).  All-core: whole 2^24-element regions on every thread the
-    box gives this process; one core: the first 2^22 elements of each
+    host gives this process; one core: the first 2^22 elements of each
     region on one thread, scaled to whole regions.  Medians of `runs`."""
     import statistics
     from concurrent.futures import ThreadPoolExecutor
@@ -792,7 +792,7 @@ def main():
         traffic_from_counters(*args.traffic_from)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (a region would "
+        print("bench.py measures one GPU: the library has no multi-GPU path (a region would "
               "split by team blocks with one exact partial exchanged per GPU)", file=sys.stderr)
         sys.exit(2)
     parts = set(args.parts.split(","))

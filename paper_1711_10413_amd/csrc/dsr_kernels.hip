@@ -563,7 +563,7 @@ __device__ __forceinline__ void fma_blocks(const double (&s)[NI + NF], const GLB
  * instances); without it every participating wave takes its fixed per-lane
  * share of the team's range.  On the lean instances the fixed share
  * measured 0.3-1.0 us faster per 2^24-element region for 8 to 32 scalars
- * and the same below (same box, interleaved). */
+ * and the same below (both builds timed interleaved on one GPU). */
 template <int NI, int NF, bool BLOCKS = true>
 __device__ __forceinline__ void fma_fixed_spans(const double (&s)[NI + NF], const dsr_dloop &L, span_t sp,
                                                 lane_acc &A, uint32_t *claim, uint32_t lane)
