@@ -635,6 +635,7 @@ def run_served(torch, np, D, W, stream, rates, seconds, pool=1000, seed=4, slots
     want = [R.exact_sum(oracle_y(q)) for q in range(pool)]
     b = D.dsr_batch_create(ctx, regs)
     res = {"pool_instances": pool, "seconds_per_rate": seconds, "slots": slots,
+           "templates": "frozen before the server starts (frame images over 1 KiB read from HBM)",
            "request_to_instance": "request q runs instance prog[q], drawn uniformly from the pool "
                                   "(seeded per rate)"}
     rng = np.random.default_rng(seed)
