@@ -523,7 +523,7 @@ def build_programs(D, W, ctx, Ls, Fs, offs, seed, x_ptr, y_ptr, chunk):
     return regs, insts
 
 
-def run_batched(torch, np, D, W, stream, n_inst=10000, seed=3, sample=64):
+def run_batched(torch, np, D, W, stream, n_inst=10000, seed=3, sample=64, each=True):
     from oracle import ref as R
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
@@ -575,13 +575,16 @@ def run_batched(torch, np, D, W, stream, n_inst=10000, seed=3, sample=64):
         ok &= (stq == 0 and f64 == R.exact_sum(yr) and fixed == R.fixed75_sum(yr))
         ok &= bool(np.array_equal(y[lo:hi].cpu().numpy(), yr))
     # one launch per region, under the tuned configuration and under plain
-    # 256-thread teams; the comparison takes the faster of the two
-    each_tuned = measure(D.dsr_batch_launch_each, 2)
-    each_tuned["tune"] = "tuned"
-    D.dsr_batch_tune(b, wg_size=256, lds_slab_bytes=65536, master_joins=1, use_graph=0)
-    each_256 = measure(D.dsr_batch_launch_each, 2)
-    each_256["tune"] = "256 threads, 64 KiB LDS stack, master joins"
-    each = min((each_tuned, each_256), key=lambda e: e["ms"])
+    # 256-thread teams; the comparison takes the faster of the two (skipped
+    # when profiling the persistent launch: 40,000 launches)
+    each_res = None
+    if each:
+        each_tuned = measure(D.dsr_batch_launch_each, 2)
+        each_tuned["tune"] = "tuned"
+        D.dsr_batch_tune(b, wg_size=256, lds_slab_bytes=65536, master_joins=1, use_graph=0)
+        each_256 = measure(D.dsr_batch_launch_each, 2)
+        each_256["tune"] = "256 threads, 64 KiB LDS stack, master joins"
+        each_res = min((each_tuned, each_256), key=lambda e: e["ms"])
     D.dsr_batch_tune(b, **{k: best[k] for k in ("wg_size", "lds_slab_bytes", "overflow_threshold",
                                                  "master_joins", "grid")}, use_graph=0)
     plain = measure(D.dsr_batch_launch, 3)
@@ -594,9 +597,9 @@ def run_batched(torch, np, D, W, stream, n_inst=10000, seed=3, sample=64):
             "autotune_ms": {"%d/%d/%d" % (c["wg_size"], c["lds_slab_bytes"], c["master_joins"]): m
                             for c, m in zip(cands, ms)},
             "persistent_graph": pers, "persistent_no_graph": plain,
-            "one_launch_per_region": each,
-            "one_launch_per_region_ms": {"tuned": each_tuned["ms"], "256": each_256["ms"]},
-            "speedup_vs_one_launch": each["ms"] / pers["ms"],
+            "one_launch_per_region": each_res,
+            "one_launch_per_region_ms": {"tuned": each_tuned["ms"], "256": each_256["ms"]} if each else None,
+            "speedup_vs_one_launch": each_res["ms"] / pers["ms"] if each else None,
             "verified_sample": {"instances": sample, "ok": bool(ok)}}
 
 
@@ -773,6 +776,8 @@ def main():
     ap.add_argument("--parts", default="sweep,ceiling,plain,arrays,lists,batched,served,cpu",
                     help="comma list of: sweep ceiling plain arrays lists batched served cpu calib")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-batched-each", action="store_true",
+                    help="skip the one-launch-per-region leg of the batched part (for profiling)")
     ap.add_argument("--no-hbm-only", action="store_true")
     ap.add_argument("--no-phases", action="store_true",
                     help="skip the traced launches that measure the loop phase")
@@ -869,7 +874,7 @@ def main():
         out["arrays_nested"] = run_arrays(torch, np, D, W, stream, shapes=shapes)
     if "batched" in parts:
         say("batched")
-        out["batched"] = run_batched(torch, np, D, W, stream)
+        out["batched"] = run_batched(torch, np, D, W, stream, each=not args.no_batched_each)
     if "served" in parts:
         say("served")
         rates = [int(v) for v in args.serve_rates.split(",") if v]
